@@ -1,0 +1,93 @@
+/*
+ * mg_oracle.h -- reference FP64 CPU multigrid for quadtree/octree block grids.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain checker that the GPU
+ * library is compared against.  Only the test-suite, the smoke check and the CPU
+ * baseline of the benchmark may load it; the product path never does.  It shares no
+ * code, header or table with the GPU library.
+ *
+ * Method: Teunissen & Keppens, "A geometric multigrid library for quadtree/octree AMR
+ * grids coupled to MPI-AMRVAC" -- operators (Sec. 2.2, eq. poisson-2d and
+ * poisson-2d-vcoeff), red-black Gauss-Seidel (Sec. 2.2), prolongation and
+ * restriction (Sec. 2.3, eq. interp_2d / interp_3d), V-cycle and FMG with the FAS
+ * coarse right-hand side (Sec. 2.4, eq. coarse-rhs and coarse-corr), grid
+ * construction with added coarse levels (Sec. 2.5, table coarse-grid-example),
+ * ghost cells and boundary conditions (Sec. 2.6).
+ */
+#ifndef MG_ORACLE_H
+#define MG_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct og_tree og_tree;
+
+/* Boundary kinds per face (-x,+x,-y,+y,-z,+z). */
+enum { OG_DIRICHLET = 0, OG_NEUMANN = 1, OG_PERIODIC = 2 };
+
+/* Refinement predicate.  level = refinement depth of the candidate block relative
+ * to the base grid (0 = base), origin = global cell index of the block's first cell
+ * on its level, bs = block size.  Non-zero = refine. */
+typedef int (*og_refine_fn)(void *ud, int domain, int level, const int32_t *origin, int bs);
+
+/* Create one tree (one domain).  Returns NULL on invalid arguments.  base_cells[d]
+ * must be a multiple of bs; bs must be a power of two. */
+og_tree *og_create(int dim, const int32_t *base_cells, const double *lo, const double *hi,
+                   const int32_t *bc_kind, const double *bc_value, int bs, int max_refine,
+                   og_refine_fn refine, void *ud, int domain_id, int variable_eps);
+void og_destroy(og_tree *t);
+
+void og_set_params(og_tree *t, int n_down, int n_up, int n_max, double abs_tol, double rel_tol);
+
+/* Structure queries. */
+int og_num_levels(const og_tree *t);
+int og_base_level(const og_tree *t);
+/* Per level (coarsest = 0): bs, ncell[3], number of blocks. */
+void og_level_info(const og_tree *t, int l, int32_t *bs, int32_t *ncell, int32_t *nblocks);
+int64_t og_num_leaf_cells(const og_tree *t);
+int og_num_leaf_blocks(const og_tree *t);
+/* Leaf layout: n_leaf_cells rows of (level - base, I, J, K). */
+void og_leaf_layout(const og_tree *t, int32_t *out);
+
+/* Data on leaf cells in leaf order. */
+void og_set_rhs(og_tree *t, const double *leaf_f);
+void og_set_eps(og_tree *t, const double *leaf_eps);
+void og_set_phi(og_tree *t, const double *leaf_phi);
+void og_get_phi(const og_tree *t, double *leaf_phi);
+
+/* Cycles. */
+void og_vcycle(og_tree *t);
+void og_fmg(og_tree *t);
+/* Composite residual on leaves: max|r|/max|f| and ||r||_2/||f||_2 (volume weighted).
+ * Side effect: parents hold the restriction of their children, ghosts refreshed. */
+void og_residual_norm(og_tree *t, double *max_rel, double *l2_rel);
+/* Composite residual r = f - L(phi) into leaf_r (same side effect). */
+void og_leaf_residual(og_tree *t, double *leaf_r);
+/* Composite operator L(phi) on leaves for the given leaf phi (overwrites phi state). */
+void og_apply(og_tree *t, const double *leaf_phi, double *leaf_out);
+/* Steps taken by the last coarsest-grid solve. */
+int og_last_coarse_steps(const og_tree *t);
+
+/* Adjoint pieces: dJ/deps per leaf cell given the state phi and the adjoint lambda.
+ * Uniform trees only (all leaves on one level); returns -1 otherwise. */
+int og_face_gradient(og_tree *t, const double *leaf_phi, const double *leaf_lambda,
+                     double *leaf_dJ_deps);
+
+/* Inspection for tests: padded (bs+2)^d copy of a field of block b on level l
+ * (index within the level's creation order).  field: 0 v, 1 f, 2 vold, 3 r, 4 eps. */
+int og_level_nblocks(const og_tree *t, int l);
+void og_block_meta(const og_tree *t, int l, int ib, int32_t *origin, int32_t *has_children);
+void og_block_field(const og_tree *t, int l, int ib, int field, double *out);
+void og_set_block_field(og_tree *t, int l, int ib, int field, const double *in);
+/* Operations on one level, exposed for the invariant tests. */
+void og_fill_ghosts_level(og_tree *t, int l);
+void og_restrict_all(og_tree *t);
+/* v^h += P(v^H - v_old^H) on level l, then ghosts of level l. */
+void og_correct_level(og_tree *t, int l);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

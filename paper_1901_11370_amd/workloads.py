@@ -1,0 +1,230 @@
+"""Seeded synthetic inputs for the multigrid workloads.
+
+This module holds no part of the solver's arithmetic: it only describes domains and
+evaluates right-hand sides, coefficients, targets and refinement predicates at cell
+centres that it computes from the integer leaf layout (level above base, I, J, K) each
+library reports.  Both the GPU library's tests/benchmark and the reference solver read
+their inputs from here, so the two always see identical arrays.
+
+Shapes follow the paper's test problems (Sec. 3): unit cubes/squares, 16^d blocks,
+Dirichlet or periodic boundaries, Gaussian sources.  Random parameters come from
+``numpy.random.default_rng(seed)``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, Optional, Sequence
+
+import numpy as np
+
+DIRICHLET, NEUMANN, PERIODIC = 0, 1, 2
+
+
+@dataclass
+class Domain:
+    dim: int
+    base_cells: Sequence[int]
+    lo: Sequence[float]
+    hi: Sequence[float]
+    bc_kind: Sequence[int]
+    bc_value: Sequence[float] = field(default_factory=lambda: [0.0] * 6)
+
+    def h_base(self):
+        return [(self.hi[d] - self.lo[d]) / self.base_cells[d] for d in range(self.dim)]
+
+
+def cell_centres(layout: np.ndarray, dom: Domain) -> np.ndarray:
+    """(n, dim) centres of the cells listed in an integer layout (level, I, J, K)."""
+    layout = np.asarray(layout)
+    out = np.empty((layout.shape[0], dom.dim))
+    scale = 2.0 ** layout[:, 0].astype(np.float64)
+    for d in range(dom.dim):
+        h = (dom.hi[d] - dom.lo[d]) / dom.base_cells[d] / scale
+        out[:, d] = dom.lo[d] + (layout[:, d + 1] + 0.5) * h
+    return out
+
+
+def cell_widths(layout: np.ndarray, dom: Domain) -> np.ndarray:
+    scale = 2.0 ** np.asarray(layout)[:, 0].astype(np.float64)
+    return np.stack([(dom.hi[d] - dom.lo[d]) / dom.base_cells[d] / scale for d in range(dom.dim)], axis=1)
+
+
+def block_centres(dom: Domain, level: int, origin, bs: int) -> np.ndarray:
+    """Centres of the bs^d cells of a block given its level (above base) and origin."""
+    ax = []
+    for d in range(dom.dim):
+        h = (dom.hi[d] - dom.lo[d]) / dom.base_cells[d] / 2.0 ** level
+        ax.append(dom.lo[d] + (origin[d] + 0.5 + np.arange(bs)) * h)
+    g = np.meshgrid(*ax, indexing="ij")
+    return np.stack([x.ravel() for x in g], axis=1)
+
+
+# ----------------------------------------------------------------- sources
+@dataclass
+class Gaussians:
+    centres: np.ndarray     # (k, dim)
+    amps: np.ndarray        # (k,)
+    sigmas: np.ndarray      # (k,)
+    periodic: bool = False
+
+    def __call__(self, x: np.ndarray) -> np.ndarray:
+        out = np.zeros(x.shape[0])
+        for c, a, s in zip(self.centres, self.amps, self.sigmas):
+            d = x - c
+            if self.periodic:
+                d = d - np.round(d)
+            out += a * np.exp(-np.sum(d * d, axis=1) / (s * s))
+        return out
+
+
+def sine_rhs_2d(x):
+    """f = -2 pi^2 sin(pi x) sin(pi y), whose solution is sin(pi x) sin(pi y)."""
+    return -2.0 * np.pi ** 2 * np.sin(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1])
+
+
+# --------------------------------------------------------------- workloads
+@dataclass
+class Workload:
+    name: str
+    domains: list
+    bs: int = 16
+    max_refine: int = 0
+    refine: Optional[Callable] = None   # refine(domain, level, origin, bs) -> bool
+    variable_eps: bool = False
+    rhs: Optional[Callable] = None      # rhs(domain_index, layout) -> f
+    eps: Optional[Callable] = None      # eps(domain_index, layout) -> eps
+    target: Optional[Callable] = None
+    note: str = ""
+
+
+def _unit(dim, n, bc):
+    return Domain(dim, [n] * dim, [0.0] * dim, [1.0] * dim, [bc] * (2 * dim))
+
+
+def config1(n: int = 128) -> Workload:
+    """2D Poisson on the unit square, 128^2 cells in 16^2 blocks, phi = 0 on the
+    boundary, f from the manufactured phi = sin(pi x) sin(pi y)."""
+    dom = _unit(2, n, DIRICHLET)
+    return Workload("poisson2d_128_dirichlet_sine", [dom],
+                    rhs=lambda i, lay: sine_rhs_2d(cell_centres(lay, dom)))
+
+
+def config2(n: int = 256, seed: int = 2) -> Workload:
+    """3D periodic Poisson, n^3 cells in 16^3 blocks; f = sum of 32 Gaussians
+    (sigma 0.02, centres uniform, amplitudes +-1, minimum-image distance), with the
+    discrete mean removed."""
+    rng = np.random.default_rng(seed)
+    centres = rng.random((32, 3))
+    amps = np.where(rng.random(32) < 0.5, -1.0, 1.0)
+    g = Gaussians(centres, amps, np.full(32, 0.02), periodic=True)
+    dom = _unit(3, n, PERIODIC)
+
+    def rhs(i, lay):
+        f = g(cell_centres(lay, dom))
+        return f - f.mean()
+    return Workload(f"poisson3d_{n}_periodic_32gauss", [dom], rhs=rhs)
+
+
+def _config3_sources(seed=3):
+    rng = np.random.default_rng(seed)
+    sig = rng.uniform(0.005, 0.02, 4)
+    centres = rng.uniform(0.1, 0.9, (4, 3))
+    amps = np.where(rng.random(4) < 0.5, -1.0, 1.0)
+    return Gaussians(centres, amps, sig)
+
+
+def config3(nested: bool = True, base: int = 128, seed: int = 3) -> Workload:
+    """3D AMR octree, base 128^3 in 16^3 blocks, 3 refinement levels, phi = 0 on the
+    boundary, f = 4 Gaussians (sigma 0.005-0.02).
+
+    nested=False: the literal rule, a block is refined where |f| > 0.05 max|a_k| at
+    one of its cell centres.  nested=True: the paper-shaped nested layout of about
+    1.16e8 leaf cells (level 1 everywhere, level 2 on [0.125,0.875]^3, level 3 on
+    [0.3125,0.6875]^3) with the same f."""
+    g = _config3_sources(seed)
+    dom = _unit(3, base, DIRICHLET)
+    thr = 0.05 * np.max(np.abs(g.amps))
+
+    def literal(d, level, origin, bs):
+        x = block_centres(dom, level, origin, bs)
+        return bool(np.any(np.abs(g(x)) > thr))
+
+    boxes = {0: (0.0, 1.0), 1: (0.125, 0.875), 2: (0.3125, 0.6875)}
+
+    def nested_rule(d, level, origin, bs):
+        if level not in boxes:
+            return False
+        lo, hi = boxes[level]
+        h = 1.0 / (base * 2 ** level)
+        for k in range(3):
+            a, b = origin[k] * h, (origin[k] + bs) * h
+            if a < lo - 1e-12 or b > hi + 1e-12:
+                return False
+        return True
+
+    return Workload("poisson3d_amr_" + ("nested" if nested else "literal"), [dom], max_refine=3,
+                    refine=nested_rule if nested else literal,
+                    rhs=lambda i, lay: g(cell_centres(lay, dom)))
+
+
+def config4(nested: bool = True, seed: int = 4) -> Workload:
+    """Config-3 tree and f with eps = 1 + 999 s, s a linear ramp over two leaf cells
+    around three spheres of radius 0.1 (centres uniform in [0.1,0.9]^3)."""
+    w = config3(nested)
+    dom = w.domains[0]
+    rng = np.random.default_rng(seed)
+    C = rng.uniform(0.1, 0.9, (3, 3))
+
+    def eps(i, lay):
+        x = cell_centres(lay, dom)
+        hl = cell_widths(lay, dom)[:, 0]
+        s = np.zeros(x.shape[0])
+        for c in C:
+            r = np.sqrt(np.sum((x - c) ** 2, axis=1))
+            s = np.maximum(s, np.clip(0.5 - (r - 0.1) / (2.0 * hl), 0.0, 1.0))
+        return 1.0 + 999.0 * s
+    w.name = w.name.replace("poisson3d", "varcoef3d")
+    w.variable_eps = True
+    w.eps = eps
+    return w
+
+
+CONFIG5_SIZES = (64, 96, 128, 160, 192, 256)
+
+
+def _lognormal_field(n, seed, corr=8.0):
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((n, n, n))
+    k = np.fft.fftfreq(n)
+    kk = k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2
+    kern = np.exp(-2.0 * np.pi ** 2 * corr ** 2 * kk)   # Gaussian of std `corr` cells
+    g = np.real(np.fft.ifftn(np.fft.fftn(w) * kern))
+    g = (g - g.mean()) / g.std()
+    return g  # indexed [I, J, K]
+
+
+def config5(sizes: Sequence[int] = CONFIG5_SIZES) -> Workload:
+    """Batch of independent unit cubes (64^3 ... 256^3, 16^3 blocks, phi = 0 on the
+    boundary); eps = exp(0.5 g), g unit-variance noise with 8-cell Gaussian
+    correlation; f = 8 Gaussians (width 0.05, amplitudes +-1); target
+    1e-3 sin(pi x) sin(pi y) sin(pi z)."""
+    doms = [_unit(3, n, DIRICHLET) for n in sizes]
+    srcs = []
+    for i, n in enumerate(sizes):
+        rng = np.random.default_rng(510 + i)
+        c = rng.uniform(0.2, 0.8, (8, 3))
+        a = np.where(rng.random(8) < 0.5, -1.0, 1.0)
+        srcs.append(Gaussians(c, a, np.full(8, 0.05)))
+
+    def rhs(i, lay):
+        return srcs[i](cell_centres(lay, doms[i]))
+
+    def eps(i, lay):
+        g = _lognormal_field(sizes[i], 500 + i)
+        return np.exp(0.5 * g[lay[:, 1], lay[:, 2], lay[:, 3]])
+
+    def target(i, lay):
+        x = cell_centres(lay, doms[i])
+        return 1e-3 * np.prod(np.sin(np.pi * x), axis=1)
+
+    return Workload("diffsolve3d_batch6", doms, variable_eps=True, rhs=rhs, eps=eps, target=target)
