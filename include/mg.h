@@ -1,0 +1,177 @@
+/*
+ * mg.h -- C ABI of the MI355X multigrid library for quadtree/octree block grids.
+ *
+ * Solves div(eps grad phi) = f (the paper's eq. poisson) on one or more independent
+ * domains, each a quadtree (2D) or octree (3D) of bs^d-cell blocks, with the
+ * second-order cell-centred operators of Sec. 2.2 (eq. poisson-2d, poisson-2d-vcoeff),
+ * red-black Gauss-Seidel smoothing, the transfer operators of Sec. 2.3, and FAS
+ * V-cycles / FMG cycles of Sec. 2.4.  Grid construction (added coarse levels, 2:1
+ * balance) follows Sec. 2.5; ghost cells and boundary conditions Sec. 2.6.
+ *
+ * Conventions
+ *  - Every call returns an mg_status; nothing throws across the ABI.  The text of
+ *    the last error of a tree is available from mg_last_error().
+ *  - Ownership: the caller owns every array it passes and the device store it binds
+ *    (one allocation of mg_tree_storage_bytes() bytes, 256-byte aligned); the library
+ *    owns the tree's host metadata and never allocates device memory.
+ *  - Leaf order: domain, then refinement level (coarse to fine), then Morton order of
+ *    the block coordinates on that level, then cells with x fastest (then y, then z).
+ *  - Device work is asynchronous on the stream given to mg_tree_bind().  Calls that
+ *    return host values (mg_residual_norm, mg_domain_residual_norms, mg_solve, and
+ *    mg_get_phi / mg_face_gradient with host pointers) synchronise that stream.
+ *  - A tree is not thread safe; calls on one tree must not overlap.
+ */
+#ifndef MG_H
+#define MG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mg_tree mg_tree;
+
+typedef enum {
+    MG_OK = 0,
+    MG_ERR_ARG = -1,            /* invalid argument (sizes, kinds, null pointers) */
+    MG_ERR_NOT_BALANCED = -2,   /* reserved: trees built here are balanced by construction */
+    MG_ERR_DEVICE = -3,         /* a HIP call failed; mg_last_error() names it */
+    MG_ERR_NOT_CONVERGED = -4,  /* mg_solve reached max_cycles above the tolerance */
+    MG_ERR_OOM = -5,            /* the bound store is smaller than mg_tree_storage_bytes() */
+    MG_ERR_STATE = -6,          /* call out of order (e.g. cycles before mg_tree_bind) */
+    MG_ERR_NAN = -7             /* the residual norm is not finite */
+} mg_status;
+
+/* Boundary kinds (Sec. 2.6).  Dirichlet: phi = value on the face, ghost 2a - phi_i.
+ * Neumann: d phi / d x_d = value (derivative along +x_d), ghost phi_i +/- h value on
+ * the upper/lower face.  Periodic: copy across the domain (both faces of an axis). */
+typedef enum { MG_BC_DIRICHLET = 0, MG_BC_NEUMANN = 1, MG_BC_PERIODIC = 2 } mg_bc_kind;
+
+/* Faces in the order -x, +x, -y, +y, -z, +z. */
+typedef struct {
+    int32_t kind[6];
+    double value[6];
+} mg_bc;
+
+/* One independent domain: a box [lo, hi] of base_cells cells (the unrefined grid,
+ * Sec. 2.5); base_cells[d] must be a multiple of the block size. */
+typedef struct {
+    int32_t dim;            /* 2 or 3; every domain of a tree has the same dim */
+    int32_t base_cells[3];
+    double lo[3], hi[3];
+    mg_bc bc;
+} mg_domain;
+
+/* Refinement predicate, called while the tree is built for every candidate leaf
+ * block below the top level: level = refinement depth above the base grid
+ * (0 = base), origin = global index of the block's first cell on that level,
+ * bs = block size.  Non-zero refines the block.  The tree is the least 2:1 balanced
+ * tree (across faces, edges and corners) that refines every block for which the
+ * predicate holds, so the result does not depend on the calling order. */
+typedef int (*mg_refine_fn)(void *user_data, int domain, int level, const int32_t *origin,
+                            int bs);
+
+enum { MG_FP64 = 0, MG_MIXED = 1 };
+
+typedef struct {
+    int32_t n_down;           /* smoothing steps before restriction (paper default 2) */
+    int32_t n_up;             /* smoothing steps after the correction (default 2) */
+    int32_t n_max_coarse;     /* max smoothing steps on the coarsest grid (1000) */
+    double coarse_abs_tol;    /* absolute max-norm target on the coarsest grid (0) */
+    double coarse_rel_tol;    /* relative reduction on the coarsest grid (1e-8) */
+    int32_t precision;        /* MG_FP64, or MG_MIXED: FP32 cycles in FP64 refinement */
+    int32_t variable_eps;     /* 0: eps = 1, constant-coefficient stencil; 1: eps field */
+    int32_t ir_first_fmg;     /* mixed: the first refinement step runs an FP32 FMG cycle */
+    int32_t ir_vcycles;       /* mixed: FP32 V-cycles per refinement step (>= 1) */
+} mg_params;
+
+/* Fills p with the paper's defaults (Sec. 2.4) and FP64 precision. */
+int mg_default_params(mg_params *p);
+
+/* Builds the tree(s) on the host.  block_size must be 4, 8 or 16; every domain's
+ * base_cells must be multiples of it.  max_refine_levels >= 0 limits refinement
+ * above the base grid.  Returns MG_ERR_ARG for invalid input. */
+int mg_tree_create(const mg_domain *domains, int n_domains, int block_size,
+                   int max_refine_levels, mg_refine_fn refine, void *user_data,
+                   const mg_params *params, mg_tree **out);
+void mg_tree_destroy(mg_tree *t);
+
+/* Bytes of device memory the tree needs (fields of every level, index tables,
+ * staging and reduction scratch). */
+int mg_tree_storage_bytes(const mg_tree *t, size_t *bytes);
+
+/* Binds a caller-allocated device buffer of at least mg_tree_storage_bytes() bytes
+ * (256-byte aligned) and the HIP stream (hipStream_t, may be NULL for the null
+ * stream) all later work is queued on.  Uploads the tables and sets phi = 0, f = 0,
+ * eps = 1.  May be called again to move the tree to another buffer (state is reset). */
+int mg_tree_bind(mg_tree *t, void *device_store, size_t bytes, void *hip_stream);
+
+/* Structure: number of leaf cells (all domains), per-domain counts, levels. */
+int mg_num_leaf_cells(const mg_tree *t, int64_t *n);
+int mg_domain_leaf_cells(const mg_tree *t, int64_t *n_per_domain);
+int mg_num_levels(const mg_tree *t, int *n_levels);
+/* n_leaf rows of (domain, level above base, I, J, K) in leaf order. */
+int mg_leaf_layout(const mg_tree *t, int32_t *out);
+/* Blocks per level (levels with block size bs, coarsest first) and per-level cell
+ * counts; arrays of mg_num_levels() entries (tail levels of reduced block size are
+ * reported with 0 blocks). */
+int mg_level_blocks(const mg_tree *t, int32_t *n_blocks, int64_t *n_cells);
+
+/* Leaf data in leaf order, FP64.  on_device != 0: pointer to device memory.  The
+ * right-hand side and eps are inputs of later cycles; eps is restricted to every
+ * coarser level by the mean of the children (mg_set_eps requires variable_eps).
+ * mg_set_phi sets the initial guess (default 0) and makes parents the restriction
+ * of their children. */
+int mg_set_rhs(mg_tree *t, const double *leaf_f, int on_device);
+int mg_set_eps(mg_tree *t, const double *leaf_eps, int on_device);
+int mg_set_phi(mg_tree *t, const double *leaf_phi, int on_device);
+int mg_get_phi(mg_tree *t, double *leaf_phi, int on_device);
+
+/* Treat every Dirichlet/Neumann value as 0 (on != 0) -- used for adjoint solves. */
+int mg_set_homogeneous_bc(mg_tree *t, int on);
+
+/* n V-cycles (Sec. 2.4) with the tree's precision: FP64 cycles, or in MG_MIXED one
+ * FP64 refinement step of FP32 cycles per call unit.  Asynchronous. */
+int mg_vcycle(mg_tree *t, int n_cycles);
+/* n FMG cycles (Sec. 2.4, fig. mg-cycles).  Asynchronous. */
+int mg_fmg(mg_tree *t, int n_cycles);
+
+/* Composite residual over leaf cells, FP64: max|f - L phi| / max|f| and the
+ * volume-weighted L2 ratio (eq. l2-norm-example); the worst domain is returned.
+ * Side effect: parents hold the mean of their children.  Synchronises.
+ * Returns MG_ERR_NAN if the residual is not finite. */
+int mg_residual_norm(mg_tree *t, double *max_rel, double *l2_rel);
+int mg_domain_residual_norms(mg_tree *t, double *max_rel, double *l2_rel);
+
+/* Solve to max-norm relative residual <= rel_tol: optional FMG first, then V-cycles
+ * (FP64), or FP64 iterative refinement around FP32 cycles (MG_MIXED), checking the
+ * norm after every cycle / refinement step.  cycles_done may be NULL.  Returns
+ * MG_ERR_NOT_CONVERGED if max_cycles is reached first. */
+int mg_solve(mg_tree *t, double rel_tol, int max_cycles, int use_fmg_first, int *cycles_done);
+/* Per-check record of the last mg_solve: relative residual and seconds since start. */
+int mg_solve_stats(const mg_tree *t, int max_records, double *rel_residual, double *seconds,
+                   int *n_records);
+
+/* Gradient of a loss J with respect to eps, given the state phi (L phi = f) and the
+ * adjoint lambda (L^T lambda = dJ/dphi), per leaf cell: interior faces contribute
+ * h^-2 (2 eps_j^2 / (eps_i + eps_j)^2) (lambda_j - lambda_i)(phi_j - phi_i), boundary
+ * faces -h^-2 lambda_i (phi_g - phi_i).  Trees without refinement only
+ * (MG_ERR_ARG otherwise).  Overwrites the tree's phi with leaf_phi. */
+int mg_face_gradient(mg_tree *t, const double *leaf_phi, const double *leaf_lambda,
+                     double *leaf_dJ_deps, int on_device);
+
+/* Kernel timing: when enabled, HIP events bracket every launch of the smoothing
+ * kernel on the finest level (on the bound stream); mg_profile_read returns the
+ * number of such launches and their total milliseconds since enabling. */
+int mg_profile_enable(mg_tree *t, int on);
+int mg_profile_read(mg_tree *t, int64_t *launches, double *total_ms, double *bytes_per_launch);
+
+const char *mg_strerror(int status);
+const char *mg_last_error(const mg_tree *t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -16,6 +16,7 @@
 #include <string.h>
 
 #define OG_MAXLEV 40
+#define STALL 0.999   /* coarsest solve: a step must lower the residual below STALL x */
 #define NFIELD 5
 enum { F_V = 0, F_F = 1, F_VOLD = 2, F_R = 3, F_EPS = 4 };
 
@@ -684,10 +685,11 @@ static int all_periodic(const og_tree *t) {
 
 /* Coarsest grid (Sec. 2.4): smoothing steps until the max-norm residual is below the
  * absolute threshold or reduced by the relative factor, at most n_max steps, at least
- * one.  It also stops once a step no longer lowers the residual (from the second
- * step on), which only happens at the rounding floor.  On a fully periodic domain the
- * mean of f is first removed on this level so that the singular system is
- * consistent. */
+ * one.  It also stops once a step, from the second on, lowers the residual by less
+ * than 0.1%: at the rounding floor, and on a one-cell grid with Dirichlet faces, where
+ * Gauss-Seidel with the ghost held fixed only alternates between two values (the
+ * margin keeps that decision clear of rounding).  On a fully periodic domain the mean
+ * of f is first removed on this level so that the singular system is consistent. */
 static void coarse_solve(og_tree *t) {
     const OLevel *L = &t->lev[0];
     if (all_periodic(t)) {
@@ -710,7 +712,7 @@ static void coarse_solve(og_tree *t) {
         smooth_step(t, 0);
         double r = level_residual_max(t, 0);
         if (r <= target) break;
-        if (k >= 2 && r >= rprev) break;
+        if (k >= 2 && r > STALL * rprev) break;
         rprev = r;
     }
     t->last_coarse_steps = k > t->n_max ? t->n_max : k;

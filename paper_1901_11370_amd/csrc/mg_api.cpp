@@ -1,0 +1,793 @@
+// C ABI (include/mg.h) and the host-side cycle driver of the multigrid library.
+//
+// The driver walks the global levels and queues kernels on the bound stream: the
+// FAS V-cycle and FMG cycle of Sec. 2.4, the composite residual, and FP64 iterative
+// refinement around FP32 cycles.  Several domains (independent problems) share one
+// store; their levels are aligned at the bottom (every domain's reduced-block-size
+// levels occupy global levels 0..nt-1), so each level's blocks of all domains are
+// processed by one launch and every domain still sees its own cycle.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mg_internal.hpp"
+
+using namespace mgx;
+
+struct mg_tree {
+    HostTree T;
+    mg_params prm{};
+    std::string err;
+    // binding
+    char *store = nullptr;
+    size_t need = 0;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    bool homog = false;
+    // device views
+    DevTables tb{}, tb0{};          // real boundary values / homogeneous
+    Plane<double> P64{};
+    Plane<float> P32{};
+    std::vector<int32_t *> d_parents, d_cfs;
+    double *d_stage = nullptr, *d_stage2 = nullptr;
+    int32_t *d_steps = nullptr;
+    double *d_partials = nullptr, *d_domnorms = nullptr;
+    size_t off_tables = 0, bytes_tables = 0;
+    std::vector<char> host_tables;  // image of the table region
+    // layout bookkeeping
+    int64_t nb = 0, nleafblk = 0, nc = 0, ng = 0;
+    // stats
+    std::vector<double> stat_res, stat_sec;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> ev;      // pairs (start, stop)
+    size_t ev_used = 0;
+    int64_t prof_launches = 0;
+    double prof_ms = 0.0;
+};
+
+namespace {
+
+int fail(mg_tree *t, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (t) t->err = buf;
+    return code;
+}
+
+#define HIP_OR_FAIL(t, call)                                                                   \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) return fail(t, MG_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+int check_launch(mg_tree *t) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(t, MG_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+    return MG_OK;
+}
+
+struct Layout {
+    size_t off = 0;
+    template <typename X>
+    size_t take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        size_t o = off;
+        off += count * sizeof(X);
+        return o;
+    }
+};
+
+bool mixed(const mg_tree *t) { return t->prm.precision == MG_MIXED; }
+bool var(const mg_tree *t) { return t->prm.variable_eps != 0; }
+
+// Computes the byte offsets of every array of the store; with base != nullptr also
+// sets the device pointers.
+size_t plan(mg_tree *t, char *base) {
+    HostTree &T = t->T;
+    Layout L;
+    const int64_t nb = T.lev_first[T.nlev];
+    int64_t nc = 1;
+    for (int a = 0; a < T.dim; a++) nc *= T.bs;
+    int64_t nf = T.dim == 3 ? (int64_t)T.bs * T.bs : T.bs;
+    int64_t ng = 2 * T.dim * nf;
+    t->nb = nb; t->nc = nc; t->ng = ng;
+    t->nleafblk = (int64_t)T.leaf_blk.size();
+    auto P = [&](size_t o) { return base ? base + o : nullptr; };
+    // tables
+    size_t o_org = L.take<int32_t>(3 * nb), o_nbr = L.take<int32_t>(6 * nb), o_cf = L.take<int32_t>(6 * nb);
+    size_t o_par = L.take<int32_t>(nb), o_dom = L.take<int32_t>(nb), o_lev = L.take<int32_t>(nb);
+    size_t o_leaf = L.take<int32_t>(t->nleafblk), o_lf = L.take<int32_t>(T.ndom + 1);
+    size_t o_h = L.take<double>((size_t)T.ndom * MAXLEV * 3), o_nc = L.take<int32_t>((size_t)T.ndom * MAXLEV * 3);
+    size_t o_bck = L.take<int32_t>(6 * T.ndom), o_bcv = L.take<double>(6 * T.ndom), o_bc0 = L.take<double>(6 * T.ndom);
+    size_t o_toff = L.take<int64_t>((size_t)T.ndom * MAXLEV);
+    std::vector<size_t> o_parl(T.nlev), o_cfl(T.nlev);
+    for (int l = 0; l < T.nlev; l++) {
+        o_parl[l] = L.take<int32_t>(T.parents_of_level[l].size());
+        o_cfl[l] = L.take<int32_t>(T.cf_of_level[l].size());
+    }
+    t->off_tables = 0;
+    t->bytes_tables = L.off;
+    if (base) {
+        // host image of the tables
+        std::vector<char> &img = t->host_tables;
+        img.assign(L.off, 0);
+        auto put = [&](size_t o, const void *src, size_t n) { if (n) memcpy(img.data() + o, src, n); };
+        put(o_org, T.org.data(), T.org.size() * 4);
+        put(o_nbr, T.nbr.data(), T.nbr.size() * 4);
+        put(o_cf, T.cf.data(), T.cf.size() * 4);
+        put(o_par, T.parent.data(), T.parent.size() * 4);
+        put(o_dom, T.dom.data(), T.dom.size() * 4);
+        put(o_lev, T.lev.data(), T.lev.size() * 4);
+        put(o_leaf, T.leaf_blk.data(), T.leaf_blk.size() * 4);
+        put(o_lf, T.leaf_first.data(), T.leaf_first.size() * 4);
+        put(o_h, T.h.data(), T.h.size() * 8);
+        put(o_nc, T.ncell.data(), T.ncell.size() * 4);
+        std::vector<int32_t> bck(6 * T.ndom);
+        std::vector<double> bcv(6 * T.ndom), bc0(6 * T.ndom, 0.0);
+        for (int i = 0; i < T.ndom; i++)
+            for (int f = 0; f < 6; f++) {
+                bck[6 * i + f] = f < 2 * T.dim ? T.doms[i].d.bc.kind[f] : MG_BC_PERIODIC;
+                bcv[6 * i + f] = f < 2 * T.dim ? T.doms[i].d.bc.value[f] : 0.0;
+            }
+        put(o_bck, bck.data(), bck.size() * 4);
+        put(o_bcv, bcv.data(), bcv.size() * 8);
+        put(o_bc0, bc0.data(), bc0.size() * 8);
+        put(o_toff, T.tail_off.data(), T.tail_off.size() * 8);
+        for (int l = 0; l < T.nlev; l++) {
+            put(o_parl[l], T.parents_of_level[l].data(), T.parents_of_level[l].size() * 4);
+            put(o_cfl[l], T.cf_of_level[l].data(), T.cf_of_level[l].size() * 4);
+        }
+        DevTables &tb = t->tb;
+        tb.org = (const int32_t *)P(o_org);
+        tb.nbr = (const int32_t *)P(o_nbr);
+        tb.cf = (const int32_t *)P(o_cf);
+        tb.parent = (const int32_t *)P(o_par);
+        tb.dom = (const int32_t *)P(o_dom);
+        tb.lev = (const int32_t *)P(o_lev);
+        tb.leaf_blk = (const int32_t *)P(o_leaf);
+        tb.leaf_first = (const int32_t *)P(o_lf);
+        tb.h = (const double *)P(o_h);
+        tb.ncell = (const int32_t *)P(o_nc);
+        tb.bck = (const int32_t *)P(o_bck);
+        tb.bcv = (const double *)P(o_bcv);
+        tb.tail_off = (const int64_t *)P(o_toff);
+        t->tb0 = tb;
+        t->tb0.bcv = (const double *)P(o_bc0);
+        t->d_parents.assign(T.nlev, nullptr);
+        t->d_cfs.assign(T.nlev, nullptr);
+        for (int l = 0; l < T.nlev; l++) {
+            t->d_parents[l] = (int32_t *)P(o_parl[l]);
+            t->d_cfs[l] = (int32_t *)P(o_cfl[l]);
+        }
+    }
+    // fields
+    auto plane = [&](auto *pl, auto tag) {
+        using TT = decltype(tag);
+        size_t ov = L.take<TT>(nb * nc), ovg = L.take<TT>(nb * ng);
+        size_t oo = L.take<TT>(nb * nc), oog = L.take<TT>(nb * ng);
+        size_t of = L.take<TT>(nb * nc);
+        size_t oe = 0, oeg = 0;
+        if (var(t)) { oe = L.take<TT>(nb * nc); oeg = L.take<TT>(nb * ng); }
+        size_t otv = L.take<TT>(T.tail_cells), oto = L.take<TT>(T.tail_cells), otf = L.take<TT>(T.tail_cells);
+        size_t ote = var(t) ? L.take<TT>(T.tail_cells) : 0;
+        if (base) {
+            pl->v = (TT *)P(ov); pl->vg = (TT *)P(ovg);
+            pl->vold = (TT *)P(oo); pl->voldg = (TT *)P(oog);
+            pl->f = (TT *)P(of);
+            pl->eps = var(t) ? (TT *)P(oe) : nullptr;
+            pl->epsg = var(t) ? (TT *)P(oeg) : nullptr;
+            pl->tv = (TT *)P(otv); pl->tvold = (TT *)P(oto); pl->tf = (TT *)P(otf);
+            pl->teps = var(t) ? (TT *)P(ote) : nullptr;
+        }
+    };
+    plane(&t->P64, double(0));
+    if (mixed(t)) plane(&t->P32, float(0));
+    size_t o_st = L.take<double>(T.nleaf_cells), o_st2 = L.take<double>(T.nleaf_cells);
+    size_t o_steps = L.take<int32_t>(T.ndom), o_part = L.take<double>(4 * std::max<int64_t>(t->nleafblk, 1));
+    size_t o_dn = L.take<double>(4 * T.ndom);
+    if (base) {
+        t->d_stage = (double *)P(o_st);
+        t->d_stage2 = (double *)P(o_st2);
+        t->d_steps = (int32_t *)P(o_steps);
+        t->d_partials = (double *)P(o_part);
+        t->d_domnorms = (double *)P(o_dn);
+    }
+    return (L.off + 255) & ~size_t(255);
+}
+
+Launch launch(mg_tree *t, bool homogeneous) {
+    Launch L;
+    L.dim = t->T.dim; L.bs = t->T.bs; L.nt = t->T.nt; L.ndom = t->T.ndom;
+    L.tb = homogeneous ? t->tb0 : t->tb;
+    L.stream = t->stream;
+    L.coarse_steps = t->d_steps;
+    L.partials = t->d_partials;
+    L.dom_norms = t->d_domnorms;
+    return L;
+}
+
+uint64_t all_mask(const mg_tree *t) {
+    return t->T.ndom >= 64 ? ~0ull : ((1ull << t->T.ndom) - 1);
+}
+
+uint64_t mask_top_at_least(const mg_tree *t, int lev) {
+    uint64_t m = 0;
+    for (int i = 0; i < t->T.ndom; i++)
+        if (t->T.doms[i].top >= lev) m |= 1ull << i;
+    return m;
+}
+
+TailParams tail_params(const mg_tree *t) {
+    TailParams tp;
+    tp.n_down = t->prm.n_down; tp.n_up = t->prm.n_up; tp.n_max = t->prm.n_max_coarse;
+    tp.abs_tol = t->prm.coarse_abs_tol; tp.rel_tol = t->prm.coarse_rel_tol;
+    return tp;
+}
+
+int lvb0(const mg_tree *t, int l) { return t->T.lev_first[l]; }
+int lvnb(const mg_tree *t, int l) { return t->T.lev_first[l + 1] - t->T.lev_first[l]; }
+
+// ------------------------------------------------------------ cycle driver
+template <typename T>
+struct Driver {
+    mg_tree *t;
+    Launch L;
+    Plane<T> P;
+    bool v;   // variable eps
+
+    void ghost_level(int l, uint64_t m) { K<T>::ghost(L, P, lvb0(t, l), lvnb(t, l), nullptr, 0, m, false, false); }
+
+    void smooth(int l, uint64_t m, int steps) {
+        const bool timed = t->prof && l == t->T.nlev - 1;
+        const int ncf = (int)t->T.cf_of_level[l].size();
+        for (int s = 0; s < steps; s++)
+            for (int c = 0; c < 2; c++) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (timed) {
+                    if (t->ev_used + 2 > t->ev.size()) {
+                        for (int q = 0; q < 64; q++) {
+                            hipEvent_t e;
+                            if (hipEventCreate(&e) == hipSuccess) t->ev.push_back(e);
+                        }
+                    }
+                    if (t->ev_used + 2 <= t->ev.size()) {
+                        e0 = t->ev[t->ev_used];
+                        e1 = t->ev[t->ev_used + 1];
+                        t->ev_used += 2;
+                        (void)hipEventRecord(e0, L.stream);
+                    }
+                }
+                K<T>::gsrb(L, P, l, lvb0(t, l), lvnb(t, l), c, m, v);
+                if (e1) (void)hipEventRecord(e1, L.stream);
+                if (ncf) K<T>::ghost(L, P, 0, 0, t->d_cfs[l], ncf, m, false, true);
+            }
+    }
+    void restrict_fas(int l, uint64_t m) {
+        K<T>::restrict_down(L, P, l, lvb0(t, l), lvnb(t, l), m, RESTRICT_FAS, v);
+        if (l > t->T.nt) {
+            ghost_level(l - 1, m);
+            K<T>::fas(L, P, l - 1, t->d_parents[l - 1], (int)t->T.parents_of_level[l - 1].size(), m, v);
+        }
+    }
+    void correct(int l, uint64_t m) {
+        K<T>::correct(L, P, l, lvb0(t, l), lvnb(t, l), m);
+        ghost_level(l, m);
+    }
+    void vcycle(int top, uint64_t m) {
+        const int nt = t->T.nt;
+        for (int l = top; l >= nt; l--) {
+            smooth(l, m, t->prm.n_down);
+            restrict_fas(l, m);
+        }
+        K<T>::tail(L, P, TAIL_VCYCLE, m, tail_params(t), v);
+        for (int l = nt; l <= top; l++) {
+            correct(l, m);
+            smooth(l, m, t->prm.n_up);
+        }
+    }
+    void fmg() {
+        const int nt = t->T.nt, top = t->T.nlev - 1;
+        const uint64_t all = all_mask(t);
+        for (int l = top; l >= nt; l--) restrict_fas(l, all);
+        K<T>::tail(L, P, TAIL_FMG, all, tail_params(t), v);
+        for (int l = nt; l <= top; l++) {
+            uint64_t m = mask_top_at_least(t, l);
+            correct(l, m);
+            vcycle(l, m);
+        }
+    }
+    // Parents take the mean of their children, then ghosts from coarse to fine.
+    void sync() {
+        const int nt = t->T.nt, top = t->T.nlev - 1;
+        const uint64_t all = all_mask(t);
+        for (int l = top; l > nt; l--) K<T>::restrict_down(L, P, l, lvb0(t, l), lvnb(t, l), all, RESTRICT_V, false);
+        for (int l = nt; l <= top; l++) ghost_level(l, all);
+    }
+};
+
+Driver<double> d64(mg_tree *t) { return Driver<double>{t, launch(t, t->homog), t->P64, var(t)}; }
+Driver<float> d32(mg_tree *t) { return Driver<float>{t, launch(t, true), t->P32, var(t)}; }
+
+// FP64 composite residual; r may be written into the FP32 right-hand side.
+int residual64(mg_tree *t, bool write_r32, std::vector<double> *norms) {
+    Driver<double> D = d64(t);
+    D.sync();
+    launch_norm64(D.L, t->P64, (int)t->nleafblk, var(t), write_r32 ? t->P32.f : nullptr, nullptr);
+    launch_reduce_norms(D.L);
+    int rc = check_launch(t);
+    if (rc) return rc;
+    if (norms) {
+        norms->assign(4 * t->T.ndom, 0.0);
+        HIP_OR_FAIL(t, hipMemcpyAsync(norms->data(), t->d_domnorms, norms->size() * 8, hipMemcpyDeviceToHost, t->stream));
+        HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));
+    }
+    return MG_OK;
+}
+
+void rel_norms(const mg_tree *t, const std::vector<double> &n, double *mx, double *l2) {
+    for (int i = 0; i < t->T.ndom; i++) {
+        const double *p = &n[4 * i];
+        mx[i] = p[2] > 0 ? p[0] / p[2] : p[0];
+        l2[i] = p[3] > 0 ? std::sqrt(p[1] / p[3]) : std::sqrt(p[1]);
+    }
+}
+
+int worst(const mg_tree *t, const std::vector<double> &n, double *mx, double *l2) {
+    std::vector<double> a(t->T.ndom), b(t->T.ndom);
+    rel_norms(t, n, a.data(), b.data());
+    double m = 0, q = 0;
+    bool bad = false;
+    for (int i = 0; i < t->T.ndom; i++) {
+        if (!std::isfinite(a[i]) || !std::isfinite(b[i])) bad = true;
+        m = std::max(m, a[i]);
+        q = std::max(q, b[i]);
+    }
+    if (mx) *mx = bad ? NAN : m;
+    if (l2) *l2 = bad ? NAN : q;
+    return bad ? MG_ERR_NAN : MG_OK;
+}
+
+// One step of iterative refinement: r = f - L phi in FP64 (also the norm), then the
+// FP32 correction solve L e = r with zero initial guess and homogeneous boundary
+// values, then phi += e on the leaves.
+int ir_correction(mg_tree *t, bool use_fmg) {
+    Driver<float> D = d32(t);
+    const Plane<float> &P = t->P32;
+    K<float>::zero(D.L, P.v, (size_t)(t->nb * t->nc));
+    K<float>::zero(D.L, P.vg, (size_t)(t->nb * t->ng));
+    K<float>::zero(D.L, P.tv, (size_t)t->T.tail_cells);
+    if (use_fmg) {
+        D.fmg();
+    } else {
+        for (int c = 0; c < std::max(1, t->prm.ir_vcycles); c++) D.vcycle(t->T.nlev - 1, all_mask(t));
+    }
+    launch_add_leaf(D.L, t->P64.v, P.v, (int)t->nleafblk);
+    return check_launch(t);
+}
+
+int require_bound(mg_tree *t) {
+    if (!t) return MG_ERR_ARG;
+    if (!t->bound) return fail(t, MG_ERR_STATE, "tree is not bound to a device store");
+    return MG_OK;
+}
+
+const double *stage_in(mg_tree *t, const double *src, int on_device, double *stage, int *rc) {
+    *rc = MG_OK;
+    if (on_device) return src;
+    hipError_t e = hipMemcpyAsync(stage, src, (size_t)t->T.nleaf_cells * 8, hipMemcpyHostToDevice, t->stream);
+    if (e != hipSuccess) *rc = fail(t, MG_ERR_DEVICE, "hipMemcpyAsync: %s", hipGetErrorString(e));
+    return stage;
+}
+
+template <typename E>
+void prep_eps(mg_tree *t, const Launch &L, const Plane<E> &P, const double *src) {
+    K<E>::scatter(L, P.eps, src, (int)t->nleafblk);
+    const int nt = t->T.nt, top = t->T.nlev - 1;
+    for (int l = top; l >= nt; l--) K<E>::restrict_down(L, P, l, lvb0(t, l), lvnb(t, l), all_mask(t), RESTRICT_EPS, false);
+    for (int l = nt; l <= top; l++) K<E>::ghost(L, P, lvb0(t, l), lvnb(t, l), nullptr, 0, all_mask(t), true, false);
+    K<E>::tail_eps(L, P);
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+int mg_default_params(mg_params *p) {
+    if (!p) return MG_ERR_ARG;
+    memset(p, 0, sizeof *p);
+    p->n_down = 2;
+    p->n_up = 2;
+    p->n_max_coarse = 1000;
+    p->coarse_abs_tol = 0.0;
+    p->coarse_rel_tol = 1e-8;
+    p->precision = MG_FP64;
+    p->variable_eps = 0;
+    p->ir_first_fmg = 1;
+    p->ir_vcycles = 1;
+    return MG_OK;
+}
+
+int mg_tree_create(const mg_domain *domains, int n_domains, int block_size, int max_refine_levels,
+                   mg_refine_fn refine, void *user_data, const mg_params *params, mg_tree **out) {
+    if (!out) return MG_ERR_ARG;
+    *out = nullptr;
+    mg_tree *t = new mg_tree();
+    if (params) t->prm = *params;
+    else mg_default_params(&t->prm);
+    const mg_params &p = t->prm;
+    if (p.n_down < 0 || p.n_up < 0 || p.n_max_coarse < 1 || p.coarse_rel_tol < 0 || p.coarse_abs_tol < 0 ||
+        (p.precision != MG_FP64 && p.precision != MG_MIXED) || p.ir_vcycles < 1) {
+        delete t;
+        return MG_ERR_ARG;
+    }
+    std::string e = build_tree(t->T, domains, n_domains, block_size, max_refine_levels, refine, user_data);
+    if (!e.empty()) {
+        delete t;
+        return MG_ERR_ARG;
+    }
+    t->need = plan(t, nullptr);
+    *out = t;
+    return MG_OK;
+}
+
+void mg_tree_destroy(mg_tree *t) {
+    if (!t) return;
+    for (hipEvent_t e : t->ev) (void)hipEventDestroy(e);
+    delete t;
+}
+
+int mg_tree_storage_bytes(const mg_tree *t, size_t *bytes) {
+    if (!t || !bytes) return MG_ERR_ARG;
+    *bytes = t->need;
+    return MG_OK;
+}
+
+int mg_tree_bind(mg_tree *t, void *device_store, size_t bytes, void *hip_stream) {
+    if (!t || !device_store) return MG_ERR_ARG;
+    if (((uintptr_t)device_store) & 255) return fail(t, MG_ERR_ARG, "store must be 256-byte aligned");
+    if (bytes < t->need) return fail(t, MG_ERR_OOM, "store has %zu bytes, %zu needed", bytes, t->need);
+    t->store = (char *)device_store;
+    t->stream = (hipStream_t)hip_stream;
+    plan(t, t->store);
+    HIP_OR_FAIL(t, hipMemcpyAsync(t->store, t->host_tables.data(), t->host_tables.size(), hipMemcpyHostToDevice,
+                                  t->stream));
+    t->bound = true;
+    t->homog = false;
+    // phi = 0, f = 0, eps = 1 everywhere; ghosts of the block levels filled.
+    Launch L = launch(t, false);
+    auto init = [&](auto &P, auto one) {
+        using TT = decltype(one);
+        K<TT>::zero(L, P.v, (size_t)(t->nb * t->nc));
+        K<TT>::zero(L, P.vg, (size_t)(t->nb * t->ng));
+        K<TT>::zero(L, P.vold, (size_t)(t->nb * t->nc));
+        K<TT>::zero(L, P.voldg, (size_t)(t->nb * t->ng));
+        K<TT>::zero(L, P.f, (size_t)(t->nb * t->nc));
+        K<TT>::zero(L, P.tv, (size_t)t->T.tail_cells);
+        K<TT>::zero(L, P.tvold, (size_t)t->T.tail_cells);
+        K<TT>::zero(L, P.tf, (size_t)t->T.tail_cells);
+        if (var(t)) {
+            K<TT>::fill(L, P.eps, (size_t)(t->nb * t->nc), one);
+            K<TT>::fill(L, P.epsg, (size_t)(t->nb * t->ng), one);
+            K<TT>::fill(L, P.teps, (size_t)t->T.tail_cells, one);
+        }
+    };
+    init(t->P64, double(1));
+    if (mixed(t)) init(t->P32, float(1));
+    Driver<double> D = d64(t);
+    for (int l = t->T.nt; l < t->T.nlev; l++) D.ghost_level(l, all_mask(t));
+    return check_launch(t);
+}
+
+int mg_num_leaf_cells(const mg_tree *t, int64_t *n) {
+    if (!t || !n) return MG_ERR_ARG;
+    *n = t->T.nleaf_cells;
+    return MG_OK;
+}
+
+int mg_domain_leaf_cells(const mg_tree *t, int64_t *n) {
+    if (!t || !n) return MG_ERR_ARG;
+    for (int i = 0; i < t->T.ndom; i++) n[i] = t->T.dom_leaf_cells[i];
+    return MG_OK;
+}
+
+int mg_num_levels(const mg_tree *t, int *n) {
+    if (!t || !n) return MG_ERR_ARG;
+    *n = t->T.nlev;
+    return MG_OK;
+}
+
+int mg_level_blocks(const mg_tree *t, int32_t *n_blocks, int64_t *n_cells) {
+    if (!t || !n_blocks || !n_cells) return MG_ERR_ARG;
+    const HostTree &T = t->T;
+    for (int l = 0; l < T.nlev; l++) {
+        n_blocks[l] = T.lev_first[l + 1] - T.lev_first[l];
+        int64_t c = 0;
+        if (l >= T.nt) {
+            c = (int64_t)n_blocks[l] * t->nc;
+        } else {
+            for (int i = 0; i < T.ndom; i++) {
+                int64_t p = 1;
+                for (int a = 0; a < T.dim; a++) p *= T.ncell[((size_t)i * MAXLEV + l) * 3 + a];
+                c += p;
+            }
+        }
+        n_cells[l] = c;
+    }
+    return MG_OK;
+}
+
+int mg_leaf_layout(const mg_tree *t, int32_t *out) {
+    if (!t || !out) return MG_ERR_ARG;
+    const HostTree &T = t->T;
+    int64_t n = 0;
+    const int bs = T.bs;
+    for (size_t r = 0; r < T.leaf_blk.size(); r++) {
+        int b = T.leaf_blk[r];
+        int dm = T.dom[b];
+        int rel = T.lev[b] - T.doms[dm].base;
+        int kz = T.dim == 3 ? bs : 1;
+        for (int k = 0; k < kz; k++)
+            for (int j = 0; j < bs; j++)
+                for (int i = 0; i < bs; i++) {
+                    out[5 * n + 0] = dm;
+                    out[5 * n + 1] = rel;
+                    out[5 * n + 2] = T.org[3 * b] + i;
+                    out[5 * n + 3] = T.org[3 * b + 1] + j;
+                    out[5 * n + 4] = T.org[3 * b + 2] + k;
+                    n++;
+                }
+    }
+    return MG_OK;
+}
+
+int mg_set_rhs(mg_tree *t, const double *leaf_f, int on_device) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!leaf_f) return MG_ERR_ARG;
+    const double *src = stage_in(t, leaf_f, on_device, t->d_stage, &rc);
+    if (rc) return rc;
+    K<double>::scatter(launch(t, false), t->P64.f, src, (int)t->nleafblk);
+    return check_launch(t);
+}
+
+int mg_set_eps(mg_tree *t, const double *leaf_eps, int on_device) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!leaf_eps) return MG_ERR_ARG;
+    if (!var(t)) return fail(t, MG_ERR_STATE, "tree was created with variable_eps = 0");
+    const double *src = stage_in(t, leaf_eps, on_device, t->d_stage, &rc);
+    if (rc) return rc;
+    prep_eps<double>(t, launch(t, false), t->P64, src);
+    if (mixed(t)) prep_eps<float>(t, launch(t, true), t->P32, src);
+    return check_launch(t);
+}
+
+int mg_set_phi(mg_tree *t, const double *leaf_phi, int on_device) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!leaf_phi) return MG_ERR_ARG;
+    const double *src = stage_in(t, leaf_phi, on_device, t->d_stage, &rc);
+    if (rc) return rc;
+    Driver<double> D = d64(t);
+    K<double>::scatter(D.L, t->P64.v, src, (int)t->nleafblk);
+    D.sync();
+    return check_launch(t);
+}
+
+int mg_get_phi(mg_tree *t, double *leaf_phi, int on_device) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!leaf_phi) return MG_ERR_ARG;
+    double *dst = on_device ? leaf_phi : t->d_stage;
+    K<double>::gather(launch(t, false), t->P64.v, dst, (int)t->nleafblk);
+    if ((rc = check_launch(t))) return rc;
+    if (!on_device) {
+        HIP_OR_FAIL(t, hipMemcpyAsync(leaf_phi, dst, (size_t)t->T.nleaf_cells * 8, hipMemcpyDeviceToHost, t->stream));
+        HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));
+    }
+    return MG_OK;
+}
+
+int mg_set_homogeneous_bc(mg_tree *t, int on) {
+    if (!t) return MG_ERR_ARG;
+    t->homog = on != 0;
+    return MG_OK;
+}
+
+int mg_vcycle(mg_tree *t, int n) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (n < 0) return MG_ERR_ARG;
+    for (int c = 0; c < n; c++) {
+        if (mixed(t)) {
+            if ((rc = residual64(t, true, nullptr))) return rc;
+            if ((rc = ir_correction(t, false))) return rc;
+        } else {
+            d64(t).vcycle(t->T.nlev - 1, all_mask(t));
+        }
+    }
+    return check_launch(t);
+}
+
+int mg_fmg(mg_tree *t, int n) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (n < 0) return MG_ERR_ARG;
+    for (int c = 0; c < n; c++) {
+        if (mixed(t)) {
+            if ((rc = residual64(t, true, nullptr))) return rc;
+            if ((rc = ir_correction(t, true))) return rc;
+        } else {
+            d64(t).fmg();
+        }
+    }
+    return check_launch(t);
+}
+
+int mg_domain_residual_norms(mg_tree *t, double *max_rel, double *l2_rel) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!max_rel || !l2_rel) return MG_ERR_ARG;
+    std::vector<double> n;
+    if ((rc = residual64(t, false, &n))) return rc;
+    rel_norms(t, n, max_rel, l2_rel);
+    return MG_OK;
+}
+
+int mg_residual_norm(mg_tree *t, double *max_rel, double *l2_rel) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    std::vector<double> n;
+    if ((rc = residual64(t, false, &n))) return rc;
+    return worst(t, n, max_rel, l2_rel);
+}
+
+int mg_solve(mg_tree *t, double rel_tol, int max_cycles, int use_fmg_first, int *cycles_done) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (max_cycles < 0 || !(rel_tol >= 0)) return MG_ERR_ARG;
+    t->stat_res.clear();
+    t->stat_sec.clear();
+    auto t0 = std::chrono::steady_clock::now();
+    auto record = [&](double r) {
+        t->stat_res.push_back(r);
+        t->stat_sec.push_back(std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    };
+    int cycles = 0;
+    double rel = INFINITY;
+    std::vector<double> n;
+    if (!mixed(t)) {
+        if (use_fmg_first && max_cycles > 0) {
+            d64(t).fmg();
+            cycles++;
+        }
+        for (;;) {
+            if ((rc = residual64(t, false, &n))) return rc;
+            rc = worst(t, n, &rel, nullptr);
+            record(rel);
+            if (rc) break;
+            if (rel <= rel_tol || cycles >= max_cycles) break;
+            d64(t).vcycle(t->T.nlev - 1, all_mask(t));
+            cycles++;
+        }
+    } else {
+        for (;;) {
+            if ((rc = residual64(t, true, &n))) return rc;
+            rc = worst(t, n, &rel, nullptr);
+            record(rel);
+            if (rc) break;
+            if (rel <= rel_tol || cycles >= max_cycles) break;
+            if ((rc = ir_correction(t, cycles == 0 && use_fmg_first && t->prm.ir_first_fmg))) return rc;
+            cycles++;
+        }
+    }
+    if (cycles_done) *cycles_done = cycles;
+    if (rc) return rc;
+    if ((rc = check_launch(t))) return rc;
+    return rel <= rel_tol ? MG_OK : MG_ERR_NOT_CONVERGED;
+}
+
+int mg_solve_stats(const mg_tree *t, int max_records, double *rel, double *sec, int *n) {
+    if (!t || !n || max_records < 0) return MG_ERR_ARG;
+    int m = std::min<int>(max_records, (int)t->stat_res.size());
+    for (int i = 0; i < m; i++) {
+        if (rel) rel[i] = t->stat_res[i];
+        if (sec) sec[i] = t->stat_sec[i];
+    }
+    *n = (int)t->stat_res.size();
+    return MG_OK;
+}
+
+int mg_face_gradient(mg_tree *t, const double *leaf_phi, const double *leaf_lambda, double *out, int on_device) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!leaf_phi || !leaf_lambda || !out) return MG_ERR_ARG;
+    if (t->T.refined) return fail(t, MG_ERR_ARG, "face gradient needs a tree without refinement");
+    if (!var(t)) return fail(t, MG_ERR_STATE, "tree was created with variable_eps = 0");
+    const double *phi = stage_in(t, leaf_phi, on_device, t->d_stage, &rc);
+    if (rc) return rc;
+    Driver<double> D = d64(t);
+    K<double>::scatter(D.L, t->P64.v, phi, (int)t->nleafblk);
+    for (int l = t->T.nt; l < t->T.nlev; l++) D.ghost_level(l, all_mask(t));
+    const double *lam = stage_in(t, leaf_lambda, on_device, t->d_stage2, &rc);
+    if (rc) return rc;
+    // lambda is held in the v_old field (with homogeneous ghost values)
+    Plane<double> Q = t->P64;
+    Q.v = t->P64.vold;
+    Q.vg = t->P64.voldg;
+    Launch L0 = launch(t, true);
+    K<double>::scatter(L0, Q.v, lam, (int)t->nleafblk);
+    for (int l = t->T.nt; l < t->T.nlev; l++)
+        K<double>::ghost(L0, Q, lvb0(t, l), lvnb(t, l), nullptr, 0, all_mask(t), false, false);
+    double *dst = on_device ? out : t->d_stage;
+    launch_face_gradient(D.L, t->P64, Q.v, Q.vg, dst, (int)t->nleafblk);
+    if ((rc = check_launch(t))) return rc;
+    if (!on_device) {
+        HIP_OR_FAIL(t, hipMemcpyAsync(out, dst, (size_t)t->T.nleaf_cells * 8, hipMemcpyDeviceToHost, t->stream));
+        HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));
+    }
+    return MG_OK;
+}
+
+int mg_profile_enable(mg_tree *t, int on) {
+    if (!t) return MG_ERR_ARG;
+    t->prof = on != 0;
+    t->ev_used = 0;
+    t->prof_launches = 0;
+    t->prof_ms = 0.0;
+    return MG_OK;
+}
+
+int mg_profile_read(mg_tree *t, int64_t *launches, double *total_ms, double *bytes_per_launch) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));
+    for (size_t i = 0; i + 1 < t->ev_used; i += 2) {
+        float ms = 0.f;
+        HIP_OR_FAIL(t, hipEventElapsedTime(&ms, t->ev[i], t->ev[i + 1]));
+        t->prof_ms += ms;
+        t->prof_launches++;
+    }
+    t->ev_used = 0;
+    if (launches) *launches = t->prof_launches;
+    if (total_ms) *total_ms = t->prof_ms;
+    if (bytes_per_launch) {
+        // one colour of one sweep on the finest level: read the other colour of v and
+        // this colour of f, write this colour of v (plus eps of both colours)
+        const int top = t->T.nlev - 1;
+        double cellsN = (double)lvnb(t, top) * (double)t->nc;
+        double elem = mixed(t) ? 4.0 : 8.0;   // precision of the cycles
+        *bytes_per_launch = cellsN * (1.5 * elem + (var(t) ? elem : 0.0));
+    }
+    return MG_OK;
+}
+
+const char *mg_strerror(int s) {
+    switch (s) {
+        case MG_OK: return "ok";
+        case MG_ERR_ARG: return "invalid argument";
+        case MG_ERR_NOT_BALANCED: return "tree not 2:1 balanced";
+        case MG_ERR_DEVICE: return "device error";
+        case MG_ERR_NOT_CONVERGED: return "not converged";
+        case MG_ERR_OOM: return "device store too small";
+        case MG_ERR_STATE: return "invalid state";
+        case MG_ERR_NAN: return "residual is not finite";
+        default: return "unknown status";
+    }
+}
+
+const char *mg_last_error(const mg_tree *t) { return t ? t->err.c_str() : "null tree"; }
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Internal declarations shared by the host driver and the HIP kernels of the
+// multigrid library.  Not part of the public ABI (that is include/mg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "mg.h"
+
+namespace mgx {
+
+constexpr int MAXLEV = 32;    // global levels (tail + block levels)
+constexpr int MAXDOM = 64;    // domains per tree (a 64-bit mask selects them)
+
+// ------------------------------------------------------------------ device view
+// Index tables of the block levels, uploaded once per bind.  Blocks are numbered
+// level-major (coarse to fine), then by domain, then in Morton order.
+struct DevTables {
+    const int32_t *org;       // [nb][3] global index of the block's first cell on its level
+    const int32_t *nbr;       // [nb][6] same-level neighbour, -1 physical face, -2 coarse-fine
+    const int32_t *cf;        // [nb][6] coarse block across a coarse-fine face, else -1
+    const int32_t *parent;    // [nb] parent block, -1: the domain's top tail grid
+    const int32_t *dom;       // [nb] domain of the block
+    const int32_t *lev;       // [nb] global level of the block
+    const int32_t *leaf_blk;  // [nleaf_blocks] blocks in leaf order
+    const int32_t *leaf_first;// [ndom+1] first leaf rank of every domain
+    const double *h;          // [ndom][MAXLEV][3] grid spacing
+    const int32_t *ncell;     // [ndom][MAXLEV][3] cells per dimension of the full level grid
+    const int32_t *bck;       // [ndom][6] boundary kinds
+    const double *bcv;        // [ndom][6] boundary values (or zeros: homogeneous)
+    const int64_t *tail_off;  // [ndom][MAXLEV] offset of a tail level's padded array (cells)
+};
+
+// Fields of one precision.  Block levels store the interior of each block split by
+// colour (the bs^d/2 cells with even global index sum first, then the odd ones, each
+// in row order, x fastest) followed by nothing else; the 2d face ghost layers are a
+// separate array ([block][face][bs^(d-1)], tangential axes in increasing order).
+// The reduced-block-size levels below the lowest block level (the "tail") are whole
+// uniform grids per domain with one ghost layer around them.
+template <typename T>
+struct Plane {
+    T *v, *vg, *vold, *voldg, *f, *eps, *epsg;
+    T *tv, *tvold, *tf, *teps;
+};
+
+struct TailParams {
+    int n_down, n_up, n_max;
+    double abs_tol, rel_tol;
+};
+
+// Launch context.
+struct Launch {
+    int dim, bs, nt;            // dimension, block size, number of tail levels
+    int ndom;
+    DevTables tb;
+    hipStream_t stream;
+    int32_t *coarse_steps;      // [ndom] device: steps taken by the last coarsest solve
+    double *partials;           // [nleaf_blocks][4] device scratch
+    double *dom_norms;          // [ndom][4] device: max|r|, sum vol r^2, max|f|, sum vol f^2
+};
+
+// Kernel launchers (mg_kernels.hip).  `b0, nb` is a contiguous block range of one
+// level; `mask` selects domains.
+template <typename T>
+struct K {
+    static void gsrb(const Launch &L, const Plane<T> &P, int lev, int b0, int nb, int colour,
+                     uint64_t mask, bool var);
+    static void ghost(const Launch &L, const Plane<T> &P, int b0, int nb, const int32_t *list,
+                      int nlist, uint64_t mask, bool eps_field, bool cf_only);
+    static void restrict_down(const Launch &L, const Plane<T> &P, int lev, int b0, int nb,
+                              uint64_t mask, int mode, bool var);
+    static void fas(const Launch &L, const Plane<T> &P, int lev, const int32_t *list, int nlist,
+                    uint64_t mask, bool var);
+    static void correct(const Launch &L, const Plane<T> &P, int lev, int b0, int nb,
+                        uint64_t mask);
+    static void tail(const Launch &L, const Plane<T> &P, int mode, uint64_t mask,
+                     const TailParams &tp, bool var);
+    static void tail_eps(const Launch &L, const Plane<T> &P);
+    static void zero(const Launch &L, T *p, size_t n);
+    static void fill(const Launch &L, T *p, size_t n, T value);
+    static void scatter(const Launch &L, T *dst, const double *src, int nleafblk);
+    static void gather(const Launch &L, const T *src, double *dst, int nleafblk);
+};
+
+enum { RESTRICT_FAS = 0, RESTRICT_V = 1, RESTRICT_EPS = 2 };
+enum { TAIL_VCYCLE = 0, TAIL_FMG = 1 };
+
+// FP64 composite residual over the leaf blocks; optionally writes r (cast) into rout.
+void launch_norm64(const Launch &L, const Plane<double> &P, int nleafblk, bool var, float *rout32,
+                   double *rout64);
+void launch_reduce_norms(const Launch &L);
+void launch_add_leaf(const Launch &L, double *v64, const float *v32, int nleafblk);
+void launch_face_gradient(const Launch &L, const Plane<double> &P, const double *lam_blocks,
+                          const double *lam_g, double *out_leaf, int nleafblk);
+
+// ------------------------------------------------------------------- host tree
+struct HDomain {
+    mg_domain d;
+    int nblev;              // block levels of this domain (bs = block size), incl. refined
+    int top;                // global level of the finest block level
+    int base;               // global level of the unrefined grid
+    int nblk_low[3];        // blocks per dim on the lowest block level
+};
+
+struct HBlock {
+    int dom, lev;
+    int bc[3];              // block coordinates on its level
+    int parent;             // index into the builder's block vector, -1 for the lowest level
+    int child[8];
+    bool has_children;
+    bool tested;
+};
+
+struct HostTree {
+    int dim = 0, bs = 0, nt = 0, ndom = 0, nlev = 0;   // nlev: global levels
+    std::vector<HDomain> doms;
+    // final numbering
+    std::vector<int32_t> org, nbr, cf, parent, dom, lev;
+    std::vector<int32_t> leaf_blk, leaf_first;
+    std::vector<int> lev_first;                 // [nlev+1] first block of every global level
+    std::vector<std::vector<int32_t>> parents_of_level, cf_of_level;
+    std::vector<double> h;                      // [ndom][MAXLEV][3]
+    std::vector<int32_t> ncell;                 // [ndom][MAXLEV][3]
+    std::vector<int64_t> tail_off;              // [ndom][MAXLEV]
+    int64_t tail_cells = 0;                     // padded cells of every tail grid
+    int64_t nleaf_cells = 0;
+    std::vector<int64_t> dom_leaf_cells;
+    bool refined = false;                       // any block above a base level
+};
+
+// Builds the host tree; returns an empty string on success, else the error text.
+std::string build_tree(HostTree &T, const mg_domain *doms, int ndom, int bs, int max_refine,
+                       mg_refine_fn refine, void *ud);
+
+}  // namespace mgx

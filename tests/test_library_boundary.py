@@ -1,0 +1,78 @@
+"""The C-ABI library loads on any host, exports every function include/mg.h declares,
+and its host-side tree builder reproduces the reference solver's grids exactly (no
+GPU needed: tree construction and the leaf layout are host code)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from helpers import gpu_tree, oracle_trees
+from paper_1901_11370_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "mg.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(mg_\w+)\s*\(", txt, re.M)))
+
+
+def test_exports_every_declared_symbol():
+    from paper_1901_11370_amd import mg
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(mg._lib, n), n
+        assert n in mg.EXPORTED, n
+
+
+def _small(name):
+    if name == "config1":
+        return W.config1()
+    if name == "config2":
+        return W.config2(n=64)
+    if name == "config3":
+        return W.config3(nested=False, base=32)
+    if name == "config3n":
+        return W.config3(nested=True, base=16)
+    if name == "config5":
+        return W.config5(sizes=(32, 48, 80))
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["config1", "config2", "config3", "config3n", "config5"])
+def test_tree_layout_matches_reference(name):
+    w = _small(name)
+    t = gpu_tree(w, bind=False)
+    ref = oracle_trees(w)
+    lay = t.leaf_layout()
+    for i, o in enumerate(ref):
+        got = lay[lay[:, 0] == i][:, 1:]
+        assert np.array_equal(got, o.leaf_layout())
+
+
+def test_full_size_layouts_match_reference():
+    # the benchmark's 256^3 periodic grid and the nested AMR grid at full size
+    w = W.config3(nested=True)
+    t = gpu_tree(w, bind=False)
+    nb, nc = t.level_blocks()
+    assert t.n_leaf == 28288 * 4096
+    assert list(nb[-4:]) == [512, 4096, 13824, 13824]
+
+
+def test_invalid_arguments_are_rejected():
+    from paper_1901_11370_amd import mg
+    d = mg.Domain(3, (24, 16, 16), (0, 0, 0), (1, 1, 1), [0] * 6)   # 24 not a multiple of 16
+    with pytest.raises(mg.MGError):
+        mg.Tree([d], bs=16, bind=False)
+    d = mg.Domain(3, (32, 32, 32), (0, 0, 0), (1, 1, 1), [2, 0, 0, 0, 0, 0])   # unpaired periodic
+    with pytest.raises(mg.MGError):
+        mg.Tree([d], bs=16, bind=False)
+    d = mg.Domain(3, (32, 32, 32), (0, 0, 0), (1, 1, 1), [0] * 6)
+    with pytest.raises(mg.MGError):
+        mg.Tree([d], bs=12, bind=False)
+    t = mg.Tree([d], bs=16, bind=False)
+    with pytest.raises(mg.MGError) as e:
+        t.vcycle()
+    assert e.value.status == mg.MG_ERR_STATE
