@@ -1,0 +1,215 @@
+"""Benchmark: time-to-1e-10 multigrid solves on one MI355X.
+
+Default workload: 3D periodic Poisson on a uniform octree of 256^3 cells in 16^3
+blocks (4096 leaf blocks), f = 32 seeded Gaussians with the mean removed, FP64, one
+FMG cycle then V(2,2) cycles until the max-norm relative residual is <= 1e-10.  One
+step = set the right-hand side from a device-resident array, reset phi to 0, and
+solve to tolerance (the norm is checked after every cycle).
+
+The JSON line reports leaf cell-updates per second (leaf cells x cycles / s), the
+time to tolerance, the same solve in mixed precision (FP32 cycles inside FP64
+iterative refinement), the HBM roofline of the finest-level smoothing kernel timed
+with HIP events on the solver's stream, and the reference CPU solver timed on a
+bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_JSON = os.path.join(ROOT, "profiles", "gsrb_fp64_poisson3d_256_counters.json")
+
+
+def _args():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--n", type=int, default=256, help="cells per axis of the benchmark grid")
+    p.add_argument("--tol", type=float, default=1e-10)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-mixed", action="store_true")
+    p.add_argument("--cpu-sample-cycles", type=int, default=1, help="V-cycles after the FMG in the CPU sample")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only run a plain device-to-device copy of this many MiB (counter calibration)")
+    return p.parse_args()
+
+
+def copy_calibration(mib):
+    """A plain copy kernel of known size: its HBM counters calibrate FETCH_SIZE /
+    WRITE_SIZE, and its event-timed rate is the practical streaming bandwidth."""
+    import torch
+    n = mib * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_mib": mib, "bytes_moved": 2 * n * 8, "ms": ms,
+                      "gbs": 2 * n * 8 / (ms * 1e-3) / 1e9}), flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("mg_kernels.hip", "mg_api.cpp", "mg_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1901_11370_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(n_cells):
+    """HBM bytes per launch of the finest-level FP64 smoothing kernel from committed
+    rocprofv3 counter runs (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+    calibration); None when absent or taken on other kernel sources."""
+    try:
+        with open(PROFILE_JSON) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash() or d.get("n_cells") != n_cells:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def run_solve(tree, f_dev, zero_dev, tol):
+    tree.set_rhs(f_dev)
+    tree.set_phi(zero_dev)
+    cycles, rc = tree.solve(rel_tol=tol, max_cycles=60, fmg_first=True, raise_on_fail=False)
+    return cycles, rc
+
+
+def timed(tree, f_dev, zero_dev, tol, steps, warmup, profile=False):
+    import torch
+    for _ in range(warmup):
+        run_solve(tree, f_dev, zero_dev, tol)
+    torch.cuda.synchronize()
+    if profile:
+        tree.profile_enable(True)
+    t0 = time.perf_counter()
+    cyc = []
+    rcs = []
+    for _ in range(steps):
+        c, rc = run_solve(tree, f_dev, zero_dev, tol)
+        cyc.append(c)
+        rcs.append(rc)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    prof = tree.profile_read() if profile else None
+    if profile:
+        tree.profile_enable(False)
+    return dt, cyc, rcs, prof
+
+
+def cpu_baseline(w, sample_cycles):
+    """The reference solver, as it stands, on the host: one FMG cycle plus
+    `sample_cycles` V-cycles of the same workload, single thread."""
+    from oracle import OracleTree
+    d = w.domains[0]
+    o = OracleTree(d.dim, d.base_cells, d.lo, d.hi, d.bc_kind, bs=w.bs)
+    lay = o.leaf_layout()
+    o.set_rhs(w.rhs(0, lay))
+    t0 = time.perf_counter()
+    o.fmg()
+    o.vcycle(sample_cycles)
+    dt = time.perf_counter() - t0
+    cycles = 1 + sample_cycles
+    return {"value": o.n_leaf * cycles / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"FMG + {sample_cycles} V-cycle(s) of the same {d.base_cells[0]}^3 problem "
+                      f"({o.n_leaf} leaf cells), {dt:.2f} s on one host thread"}
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
+              "(see DESIGN.md for how the solver would shard)", file=sys.stderr)
+        sys.exit(2)
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration)
+        return
+    import numpy as np
+    import torch
+    from paper_1901_11370_amd import mg
+    from paper_1901_11370_amd import workloads as W
+
+    w = W.config2(n=a.n)
+    d = w.domains[0]
+    dom = mg.Domain(d.dim, d.base_cells, d.lo, d.hi, d.bc_kind)
+    t64 = mg.Tree([dom], bs=16, params=mg.default_params(precision=mg.MG_FP64))
+    lay = t64.leaf_layout()
+    f = w.rhs(0, lay[:, 1:])
+    f_dev = torch.from_numpy(f).to("cuda")
+    zero_dev = torch.zeros_like(f_dev)
+    nb, ncell = t64.level_blocks()
+    n_leaf = t64.n_leaf
+
+    dt, cyc, rcs, prof = timed(t64, f_dev, zero_dev, a.tol, a.steps, a.warmup, profile=True)
+    res, secs = t64.solve_stats()
+    cycles = cyc[-1]
+    # smoothing updates per cycle: every level's cells, (n_down + n_up) sweeps
+    gs_updates = float(ncell.sum()) * 4 * cycles
+    out = {
+        "metric": "cell-updates/s & time-to-1e-10 residual, FP64 vs mixed; % peak HBM",
+        "value": n_leaf * cycles / dt,
+        "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"poisson3d_{a.n}^3_periodic_32gauss_fmg+V(2,2)_to_{a.tol:g}",
+                   "leaf_cells": n_leaf, "block": "16^3", "levels": int(len(nb))},
+        "time_to_tol_ms": dt * 1e3,
+        "cycles_to_tol": cycles,
+        "converged": all(rc == 0 for rc in rcs),
+        "final_rel_residual": float(res[-1]),
+        "gs_point_updates_per_s": gs_updates / dt,
+    }
+    launches, total_ms, bytes_per = prof
+    if launches:
+        avg_ms = total_ms / launches
+        achieved = bytes_per / (avg_ms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(int(ncell[-1])),
+                           "kernel": "k_gsrb<double,3,16> finest level (one colour)",
+                           "avg_us": avg_ms * 1e3, "launches": launches,
+                           "algorithmic_bytes_per_launch": bytes_per}
+
+    if not a.no_mixed:
+        tmx = mg.Tree([dom], bs=16, params=mg.default_params(precision=mg.MG_MIXED))
+        dtm, cycm, rcsm, _ = timed(tmx, f_dev, zero_dev, a.tol, a.steps, a.warmup)
+        resm, _ = tmx.solve_stats()
+        phi64 = t64.get_phi()
+        phim = tmx.get_phi()
+        p64 = phi64 - phi64.mean()
+        pm = phim - phim.mean()
+        out["mixed"] = {"time_to_tol_ms": dtm * 1e3, "ir_steps": cycm[-1],
+                        "converged": all(rc == 0 for rc in rcsm),
+                        "final_rel_residual": float(resm[-1]),
+                        "value": n_leaf * cycm[-1] / dtm, "unit": "cell-updates/s",
+                        "speedup_vs_fp64": dt / dtm,
+                        "rel_diff_vs_fp64_solution": float(np.abs(pm - p64).max() / np.abs(p64).max())}
+        del tmx
+
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_sample_cycles)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

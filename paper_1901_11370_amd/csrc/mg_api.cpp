@@ -270,19 +270,25 @@ struct Driver {
                 }
                 K<T>::gsrb(L, P, l, lvb0(t, l), lvnb(t, l), c, m, v);
                 if (e1) (void)hipEventRecord(e1, L.stream);
-                if (ncf) K<T>::ghost(L, P, 0, 0, t->d_cfs[l], ncf, m, false, true);
+                if (ncf) cf_refresh(l, m);
             }
     }
+    // Coarse-fine ghosts of level l from the current fine and coarse values.
+    void cf_refresh(int l, uint64_t m) {
+        const int ncf = (int)t->T.cf_of_level[l].size();
+        if (ncf) K<T>::ghost(L, P, 0, 0, t->d_cfs[l], ncf, m, false, true);
+    }
+    // The restriction pushes the parents' new boundary values into the ghosts of
+    // level l-1; the other ghosts of that level are unchanged since its last update.
     void restrict_fas(int l, uint64_t m) {
         K<T>::restrict_down(L, P, l, lvb0(t, l), lvnb(t, l), m, RESTRICT_FAS, v);
-        if (l > t->T.nt) {
-            ghost_level(l - 1, m);
+        if (l > t->T.nt)
             K<T>::fas(L, P, l - 1, t->d_parents[l - 1], (int)t->T.parents_of_level[l - 1].size(), m, v);
-        }
     }
+    // The correction pushes same-level and boundary ghosts; coarse-fine ghosts follow.
     void correct(int l, uint64_t m) {
         K<T>::correct(L, P, l, lvb0(t, l), lvnb(t, l), m);
-        ghost_level(l, m);
+        cf_refresh(l, m);
     }
     void vcycle(int top, uint64_t m) {
         const int nt = t->T.nt;
@@ -322,7 +328,9 @@ Driver<float> d32(mg_tree *t) { return Driver<float>{t, launch(t, true), t->P32,
 // FP64 composite residual; r may be written into the FP32 right-hand side.
 int residual64(mg_tree *t, bool write_r32, std::vector<double> *norms) {
     Driver<double> D = d64(t);
-    D.sync();
+    // Without refinement the leaf residual uses only same-level and boundary ghosts,
+    // which every kernel keeps current; parents enter only through coarse-fine ghosts.
+    if (t->T.refined) D.sync();
     launch_norm64(D.L, t->P64, (int)t->nleafblk, var(t), write_r32 ? t->P32.f : nullptr, nullptr);
     launch_reduce_norms(D.L);
     int rc = check_launch(t);
@@ -372,7 +380,8 @@ int ir_correction(mg_tree *t, bool use_fmg) {
     } else {
         for (int c = 0; c < std::max(1, t->prm.ir_vcycles); c++) D.vcycle(t->T.nlev - 1, all_mask(t));
     }
-    launch_add_leaf(D.L, t->P64.v, P.v, (int)t->nleafblk);
+    Launch L64 = launch(t, t->homog);
+    launch_add_leaf(L64, t->P64.v, t->P64.vg, P.v, (int)t->nleafblk);
     return check_launch(t);
 }
 

@@ -93,7 +93,7 @@ enum { TAIL_VCYCLE = 0, TAIL_FMG = 1 };
 void launch_norm64(const Launch &L, const Plane<double> &P, int nleafblk, bool var, float *rout32,
                    double *rout64);
 void launch_reduce_norms(const Launch &L);
-void launch_add_leaf(const Launch &L, double *v64, const float *v32, int nleafblk);
+void launch_add_leaf(const Launch &L, double *v64, double *vg64, const float *v32, int nleafblk);
 void launch_face_gradient(const Launch &L, const Plane<double> &P, const double *lam_blocks,
                           const double *lam_g, double *out_leaf, int nleafblk);
 

@@ -31,7 +31,13 @@ struct G {
     __device__ __forceinline__ static int in(int i, int j, int k) {
         return ((i + j + k) & 1) * NH + (k * BS + j) * RH + (i >> 1);
     }
-    __device__ __forceinline__ static int gh(int f, int a1, int a2) { return f * NF + a2 * BS + a1; }
+    // Ghost faces are split by colour too: on face f the cells whose global index sum
+    // is even come first.  A ghost next to the lower face (f even) sits at local index
+    // -1, next to the upper face at BS (even), so its parity is that of a1 + a2 (+1).
+    __device__ __forceinline__ static int gpar(int f, int a1, int a2) { return (a1 + a2 + ((f & 1) ^ 1)) & 1; }
+    __device__ __forceinline__ static int gh(int f, int a1, int a2) {
+        return f * NF + gpar(f, a1, a2) * (NF / 2) + a2 * RH + (a1 >> 1);
+    }
     // Decodes the colour-storage index t (0 <= t < NC) to local coordinates.
     __device__ __forceinline__ static void decode(int t, int &i, int &j, int &k) {
         int c = t >= NH;
@@ -59,10 +65,62 @@ __device__ __forceinline__ T ld(const T *__restrict__ v, const T *__restrict__ v
     return v[b * g::NC + g::in(i, j, k)];
 }
 
+// Address of local cell (i,j,k) of block b, at most one coordinate outside [0,BS).
+template <int D, int BS, typename T>
+__device__ __forceinline__ const T *ldp(const T *v, const T *vg, int64_t b, int i, int j, int k) {
+    using g = G<D, BS>;
+    if (i < 0) return vg + b * g::NG + g::gh(0, j, k);
+    if (i >= BS) return vg + b * g::NG + g::gh(1, j, k);
+    if (j < 0) return vg + b * g::NG + g::gh(2, i, k);
+    if (j >= BS) return vg + b * g::NG + g::gh(3, i, k);
+    if (D == 3) {
+        if (k < 0) return vg + b * g::NG + g::gh(4, i, j);
+        if (k >= BS) return vg + b * g::NG + g::gh(5, i, j);
+    }
+    return v + b * g::NC + g::in(i, j, k);
+}
+
 template <typename T>
 __device__ __forceinline__ T harm(T a, T b) {
     return T(2) * a * b / (a + b);
 }
+
+// ------------------------------------------------------- LDS staging helper
+// Copies NRUN runs of LEN elements (run r at src + r * STRIDE) to dst + r * LEN with
+// the widest aligned vector loads, all of a thread's loads issued before any store,
+// so one workgroup's staging costs one memory latency instead of one per element.
+template <int B> struct VecOf;
+template <> struct VecOf<16> { using type = uint4; };
+template <> struct VecOf<8> { using type = uint2; };
+template <> struct VecOf<4> { using type = unsigned; };
+
+template <typename T, int NRUN, int LEN, int STRIDE, int TPB>
+struct Stager {
+    static constexpr int BYTES = LEN * (int)sizeof(T);
+    static constexpr int VB = BYTES % 16 == 0 ? 16 : (BYTES % 8 == 0 ? 8 : 4);
+    using V = typename VecOf<VB>::type;
+    static constexpr int CR = BYTES / VB;          // vectors per run
+    static constexpr int NCH = NRUN * CR;
+    static constexpr int IT = (NCH + TPB - 1) / TPB;
+    V r[IT];
+    // Loads are unconditional (a thread past the end re-reads the last vector) so
+    // that none of them waits behind a branch.
+    __device__ __forceinline__ void load(const T *src) {
+#pragma unroll
+        for (int m = 0; m < IT; m++) {
+            int q = (int)threadIdx.x + m * TPB;
+            if (NCH % TPB != 0) q = q < NCH ? q : NCH - 1;
+            r[m] = reinterpret_cast<const V *>(src + (size_t)(q / CR) * STRIDE)[q % CR];
+        }
+    }
+    __device__ __forceinline__ void store(T *dst) const {
+#pragma unroll
+        for (int m = 0; m < IT; m++) {
+            const int q = (int)threadIdx.x + m * TPB;
+            if (NCH % TPB == 0 || q < NCH) reinterpret_cast<V *>(dst + (q / CR) * LEN)[q % CR] = r[m];
+        }
+    }
+};
 
 struct Spacing {
     double ih2[3];
@@ -128,48 +186,118 @@ __device__ __forceinline__ T bc_ghost(int kind, double a, double h, int side, T 
     return inner + T((side ? 1.0 : -1.0) * h * a);
 }
 
-// ------------------------------------------------------------ GS-RB sweep
-// One colour of red-black Gauss-Seidel (Sec. 2.2) on a contiguous block range of one
-// level.  Each thread updates one cell of the colour and pushes the new value into
-// the ghost layer that mirrors it: the neighbour block's ghost on a same-level face,
-// its own ghost on a physical face.  Ghost positions hold the colour of the cell they
-// mirror, so a half-sweep never reads a ghost another thread writes.  Coarse-fine
-// ghosts are refreshed by a separate launch.
-template <typename T, int D, int BS, bool VAR>
-__global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev, int b0, int colour,
-                                              uint64_t mask, int wg_per_block) {
+// ------------------------------------------------------------ ghost push
+// After a cell of block b changes, the ghost that mirrors it is written: the
+// neighbour block's ghost on a same-level face, the block's own ghost (boundary
+// condition applied) on a physical face.  Coarse-fine ghosts depend on several fine
+// cells and coarse data; a separate launch refreshes them.
+template <typename T, int D, int BS>
+__device__ __forceinline__ void push_ghosts(T *__restrict__ vg, const DevTables &tb, int64_t b, int dm,
+                                            const double *hh, int i, int j, int k, T nv) {
     using g = G<D, BS>;
-    const int64_t b = b0 + blockIdx.x / wg_per_block;
-    const int dm = tb.dom[b];
-    if (!((mask >> dm) & 1)) return;
-    const int t = (blockIdx.x % wg_per_block) * blockDim.x + threadIdx.x;
-    if (t >= g::NH) return;
-    int i, j, k;
-    g::decode(colour * g::NH + t, i, j, k);
-    const Spacing s = spacing(tb, dm, lev);
-    Stencil<T, D, BS, VAR> st;
-    st.load(P, b, i, j, k, s, false);
-    const int64_t self = b * g::NC + colour * g::NH + t;
-    const T nv = st.gs(P.f[self]);
-    P.v[self] = nv;
-    // ghost push
-    const int32_t *nbr = tb.nbr + 6 * b;
-    int coord[3] = {i, j, k};
+    const int coord[3] = {i, j, k};
 #pragma unroll
     for (int a = 0; a < D; a++) {
-        int side = -1;
+        int side;
         if (coord[a] == 0) side = 0;
         else if (coord[a] == BS - 1) side = 1;
-        if (side < 0) continue;
-        int f = 2 * a + side;
-        int a1 = a == 0 ? j : i, a2 = a == 2 ? j : k;
-        int n = nbr[f];
-        if (n >= 0) {
-            P.vg[(int64_t)n * g::NG + g::gh(f ^ 1, a1, a2)] = nv;
-        } else if (n == -1) {
-            const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
-            P.vg[b * g::NG + g::gh(f, a1, a2)] = bc_ghost<T>(tb.bck[6 * dm + f], tb.bcv[6 * dm + f], hh[a], side, nv);
+        else continue;
+        const int f = 2 * a + side;
+        const int a1 = a == 0 ? j : i, a2 = a == 2 ? j : k;
+        const int n = tb.nbr[6 * b + f];
+        if (n >= 0) vg[(int64_t)n * g::NG + g::gh(f ^ 1, a1, a2)] = nv;
+        else if (n == -1) vg[b * g::NG + g::gh(f, a1, a2)] = bc_ghost<T>(tb.bck[6 * dm + f], tb.bcv[6 * dm + f], hh[a], side, nv);
+    }
+}
+
+// ------------------------------------------------------------ GS-RB sweep
+// One colour of red-black Gauss-Seidel (Sec. 2.2) for the blocks of one level, one
+// workgroup per block.  The other colour of the block and the other-colour halves of
+// its ghost faces are staged in LDS (each value read once from HBM, unit stride);
+// each thread then updates cells of this colour, reading f and writing v with unit
+// stride, and pushes boundary values into the mirroring ghosts.  A ghost position has
+// the colour of the cell it mirrors, so the sweep never reads what it writes.
+template <typename T, int D, int BS, bool VAR>
+__global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev, int b0, int colour,
+                                              uint64_t mask) {
+    using g = G<D, BS>;
+    constexpr int TPB = g::NH < 256 ? g::NH : 256;
+    constexpr int HF = g::NF / 2;               // ghosts of one colour per face
+    constexpr int NGH = 2 * D * HF;
+    constexpr int IT = g::NH / TPB;
+    __shared__ __align__(16) T s_o[g::NH];
+    __shared__ __align__(16) T s_g[NGH];
+    __shared__ __align__(16) T s_eo[VAR ? g::NH : 1];
+    __shared__ __align__(16) T s_eg[VAR ? NGH : 1];
+    const int64_t b = b0 + blockIdx.x;
+    const int dm = tb.dom[b];
+    if (!((mask >> dm) & 1)) return;
+    const int oc = colour ^ 1;
+    const int tid = threadIdx.x;
+    // issue every load of this thread first: other colour, its ghosts, own f (and eps)
+    Stager<T, 1, g::NH, 0, TPB> st_o;
+    Stager<T, 2 * D, HF, g::NF, TPB> st_g;
+    st_o.load(P.v + b * g::NC + oc * g::NH);
+    st_g.load(P.vg + b * g::NG + oc * HF);
+    T fr[IT], er[VAR ? IT : 1];
+#pragma unroll
+    for (int m = 0; m < IT; m++) fr[m] = P.f[b * g::NC + colour * g::NH + tid + m * TPB];
+    Stager<T, 1, VAR ? g::NH : 8, 0, TPB> st_eo;
+    Stager<T, 2 * D, VAR ? HF : 8, g::NF, TPB> st_eg;
+    if (VAR) {
+        st_eo.load(P.eps + b * g::NC + oc * g::NH);
+        st_eg.load(P.epsg + b * g::NG + oc * HF);
+#pragma unroll
+        for (int m = 0; m < IT; m++) er[m] = P.eps[b * g::NC + colour * g::NH + tid + m * TPB];
+    }
+    st_o.store(s_o);
+    st_g.store(s_g);
+    if (VAR) {
+        st_eo.store(s_eo);
+        st_eg.store(s_eg);
+    }
+    __syncthreads();
+    const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
+    T ih2[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) ih2[a] = T(1.0 / (hh[a] * hh[a]));
+#pragma unroll
+    for (int m = 0; m < IT; m++) {
+        const int q = tid + m * TPB;
+        const int row = q / g::RH, pos = q % g::RH;
+        const int j = row % BS, k = D == 3 ? row / BS : 0;
+        const int i = 2 * pos + ((j + k + colour) & 1);
+        // neighbour offsets in the other-colour arrays (interior or ghost half)
+        int off[6];
+        bool gho[6];
+        gho[0] = i == 0;      off[0] = gho[0] ? 0 * HF + k * g::RH + (j >> 1) : row * g::RH + ((i - 1) >> 1);
+        gho[1] = i == BS - 1; off[1] = gho[1] ? 1 * HF + k * g::RH + (j >> 1) : row * g::RH + ((i + 1) >> 1);
+        gho[2] = j == 0;      off[2] = gho[2] ? 2 * HF + k * g::RH + (i >> 1) : (row - 1) * g::RH + (i >> 1);
+        gho[3] = j == BS - 1; off[3] = gho[3] ? 3 * HF + k * g::RH + (i >> 1) : (row + 1) * g::RH + (i >> 1);
+        if (D == 3) {
+            gho[4] = k == 0;      off[4] = gho[4] ? 4 * HF + j * g::RH + (i >> 1) : (row - BS) * g::RH + (i >> 1);
+            gho[5] = k == BS - 1; off[5] = gho[5] ? 5 * HF + j * g::RH + (i >> 1) : (row + BS) * g::RH + (i >> 1);
         }
+        T num = T(0), den = T(0);
+        const T fval = fr[m];
+        if (!VAR) {
+#pragma unroll
+            for (int f = 0; f < 2 * D; f++) num += ih2[f >> 1] * (gho[f] ? s_g[off[f]] : s_o[off[f]]);
+#pragma unroll
+            for (int a = 0; a < D; a++) den += T(2) * ih2[a];
+        } else {
+            const T e0 = er[VAR ? m : 0];
+#pragma unroll
+            for (int f = 0; f < 2 * D; f++) {
+                const T en = gho[f] ? s_eg[off[f]] : s_eo[off[f]];
+                const T w = harm(e0, en) * ih2[f >> 1];
+                num += w * (gho[f] ? s_g[off[f]] : s_o[off[f]]);
+                den += w;
+            }
+        }
+        const T nv = (num - fval) / den;
+        P.v[b * g::NC + colour * g::NH + q] = nv;
+        push_ghosts<T, D, BS>(P.vg, tb, b, dm, hh, i, j, k, nv);
     }
 }
 
@@ -281,125 +409,233 @@ __device__ __forceinline__ TailGeo tail_geo(const DevTables &tb, int dm, int lev
 }
 
 // ----------------------------------------------- residual + restriction
-// For each coarse cell under a block of level `lev`: the mean of the 2^d fine values
-// (restriction, Sec. 2.3) of v, and for the FAS mode also of r = f - L v, written to
-// the parent block (v and f) or to the domain's top tail grid.  Mode RESTRICT_EPS
-// restricts the coefficient.
+// For every coarse cell under a block of level `lev`: the mean of its 2^d fine values
+// (restriction, Sec. 2.3) of v, and in the FAS mode also of r = f - L v, written to
+// the parent block (v, and R(r) into f) or to the domain's top tail grid.  One
+// workgroup per fine block; for the FAS mode the block's v with its ghosts is staged
+// in LDS.  Parent boundary values are pushed into the mirroring ghosts of the parent
+// level, so no separate ghost fill is needed before the FAS right-hand side.  Mode
+// RESTRICT_EPS restricts the coefficient instead (no push).
 template <typename T, int D, int BS, bool VAR, int MODE>
 __global__ void __launch_bounds__(256) k_restrict(Plane<T> P, DevTables tb, int lev, int b0,
-                                                  uint64_t mask, int wg_per_block, int nt) {
+                                                  uint64_t mask, int nt) {
     using g = G<D, BS>;
     constexpr int HB = BS / 2;
     constexpr int NQ = D == 3 ? HB * HB * HB : HB * HB;
-    const int64_t b = b0 + blockIdx.x / wg_per_block;
+    constexpr int TPB = NQ < 256 ? NQ : 256;
+    constexpr bool FAS = MODE == RESTRICT_FAS;
+    constexpr int IT = (NQ + TPB - 1) / TPB;
+    __shared__ __align__(16) T s_v[FAS ? g::NC + g::NG : 4];
+    const int64_t b = b0 + blockIdx.x;
     const int dm = tb.dom[b];
     if (!((mask >> dm) & 1)) return;
-    const int t = (blockIdx.x % wg_per_block) * blockDim.x + threadIdx.x;
-    if (t >= NQ) return;
-    const int ci = t % HB, cj = (t / HB) % HB, ck = D == 3 ? t / (HB * HB) : 0;
-    const Spacing s = spacing(tb, dm, lev);
-    const T *src = MODE == RESTRICT_EPS ? P.eps : P.v;
-    T sv = T(0), sr = T(0);
+    const int tid = threadIdx.x;
+    // fine values of this thread's coarse cells (the field itself, or f for FAS)
+    const T *src = MODE == RESTRICT_EPS ? P.eps : (FAS ? P.f : P.v);
+    T pre[IT][1 << D];
 #pragma unroll
-    for (int q = 0; q < (1 << D); q++) {
-        int i = 2 * ci + (q & 1), j = 2 * cj + ((q >> 1) & 1), k = D == 3 ? 2 * ck + (q >> 2) : 0;
-        sv += src[b * g::NC + g::in(i, j, k)];
-        if (MODE == RESTRICT_FAS) {
-            Stencil<T, D, BS, VAR> st;
-            st.load(P, b, i, j, k, s, true);
-            sr += P.f[b * g::NC + g::in(i, j, k)] - st.Lv();
-        }
+    for (int m = 0; m < IT; m++) {
+        const int t = (NQ % TPB == 0 || tid + m * TPB < NQ) ? tid + m * TPB : 0;
+        const int ci = t % HB, cj = (t / HB) % HB, ck = D == 3 ? t / (HB * HB) : 0;
+#pragma unroll
+        for (int q = 0; q < (1 << D); q++)
+            pre[m][q] = src[b * g::NC + g::in(2 * ci + (q & 1), 2 * cj + ((q >> 1) & 1), D == 3 ? 2 * ck + (q >> 2) : 0)];
     }
-    const T inv = T(1) / T(1 << D);
-    sv *= inv;
-    sr *= inv;
-    int gc[3] = {(tb.org[3 * b] >> 1) + ci, (tb.org[3 * b + 1] >> 1) + cj, D == 3 ? (tb.org[3 * b + 2] >> 1) + ck : 0};
+    if (FAS) {
+        Stager<T, 1, g::NC, 0, TPB> st_v;
+        Stager<T, 1, g::NG, 0, TPB> st_g;
+        st_v.load(P.v + b * g::NC);
+        st_g.load(P.vg + b * g::NG);
+        st_v.store(s_v);
+        st_g.store(s_v + g::NC);
+        __syncthreads();
+    }
+    const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
+    T ih2[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) ih2[a] = T(1.0 / (hh[a] * hh[a]));
     const int64_t p = tb.parent[b];
-    if (p >= 0) {
-        int l0 = gc[0] - tb.org[3 * p], l1 = gc[1] - tb.org[3 * p + 1], l2 = D == 3 ? gc[2] - tb.org[3 * p + 2] : 0;
-        int64_t o = p * g::NC + g::in(l0, l1, l2);
-        if (MODE == RESTRICT_EPS) P.eps[o] = sv;
-        else P.v[o] = sv;
-        if (MODE == RESTRICT_FAS) P.f[o] = sr;
-    } else {
-        TailGeo tg = tail_geo(tb, dm, nt - 1, D);
-        int64_t o = tg.idx(gc[0], gc[1], gc[2], D);
-        if (MODE == RESTRICT_EPS) P.teps[o] = sv;
-        else P.tv[o] = sv;
-        if (MODE == RESTRICT_FAS) P.tf[o] = sr;
+    const int ob[3] = {tb.org[3 * b], tb.org[3 * b + 1], tb.org[3 * b + 2]};
+#pragma unroll
+    for (int m = 0; m < IT; m++) {
+        const int t = tid + m * TPB;
+        if (NQ % TPB != 0 && t >= NQ) break;
+        const int ci = t % HB, cj = (t / HB) % HB, ck = D == 3 ? t / (HB * HB) : 0;
+        T sv = T(0), sr = T(0);
+#pragma unroll
+        for (int q = 0; q < (1 << D); q++) {
+            const int i = 2 * ci + (q & 1), j = 2 * cj + ((q >> 1) & 1), k = D == 3 ? 2 * ck + (q >> 2) : 0;
+            const int c = g::in(i, j, k);
+            if (!FAS) {
+                sv += pre[m][q];
+            } else {
+                const T vc = s_v[c];
+                sv += vc;
+                T nb[6];
+                nb[0] = i > 0 ? s_v[g::in(i - 1, j, k)] : s_v[g::NC + g::gh(0, j, k)];
+                nb[1] = i < BS - 1 ? s_v[g::in(i + 1, j, k)] : s_v[g::NC + g::gh(1, j, k)];
+                nb[2] = j > 0 ? s_v[g::in(i, j - 1, k)] : s_v[g::NC + g::gh(2, i, k)];
+                nb[3] = j < BS - 1 ? s_v[g::in(i, j + 1, k)] : s_v[g::NC + g::gh(3, i, k)];
+                if (D == 3) {
+                    nb[4] = k > 0 ? s_v[g::in(i, j, k - 1)] : s_v[g::NC + g::gh(4, i, j)];
+                    nb[5] = k < BS - 1 ? s_v[g::in(i, j, k + 1)] : s_v[g::NC + g::gh(5, i, j)];
+                }
+                T lv = T(0);
+                if (!VAR) {
+#pragma unroll
+                    for (int f = 0; f < 2 * D; f++) lv += ih2[f >> 1] * (nb[f] - vc);
+                } else {
+                    const T e0 = P.eps[b * g::NC + c];
+                    T en[6];
+                    en[0] = ld<D, BS>(P.eps, P.epsg, b, i - 1, j, k);
+                    en[1] = ld<D, BS>(P.eps, P.epsg, b, i + 1, j, k);
+                    en[2] = ld<D, BS>(P.eps, P.epsg, b, i, j - 1, k);
+                    en[3] = ld<D, BS>(P.eps, P.epsg, b, i, j + 1, k);
+                    if (D == 3) {
+                        en[4] = ld<D, BS>(P.eps, P.epsg, b, i, j, k - 1);
+                        en[5] = ld<D, BS>(P.eps, P.epsg, b, i, j, k + 1);
+                    }
+#pragma unroll
+                    for (int f = 0; f < 2 * D; f++) lv += harm(e0, en[f]) * ih2[f >> 1] * (nb[f] - vc);
+                }
+                sr += pre[m][q] - lv;
+            }
+        }
+        const T inv = T(1) / T(1 << D);
+        sv *= inv;
+        sr *= inv;
+        const int gc[3] = {(ob[0] >> 1) + ci, (ob[1] >> 1) + cj, D == 3 ? (ob[2] >> 1) + ck : 0};
+        if (p >= 0) {
+            const int l0 = gc[0] - tb.org[3 * p], l1 = gc[1] - tb.org[3 * p + 1], l2 = D == 3 ? gc[2] - tb.org[3 * p + 2] : 0;
+            const int64_t o = p * g::NC + g::in(l0, l1, l2);
+            if (MODE == RESTRICT_EPS) {
+                P.eps[o] = sv;
+            } else {
+                P.v[o] = sv;
+                if (FAS) P.f[o] = sr;
+                const double *hp = tb.h + ((size_t)dm * MAXLEV + lev - 1) * 3;
+                push_ghosts<T, D, BS>(P.vg, tb, p, dm, hp, l0, l1, l2, sv);
+            }
+        } else {
+            const TailGeo tg = tail_geo(tb, dm, nt - 1, D);
+            const int64_t o = tg.idx(gc[0], gc[1], gc[2], D);
+            if (MODE == RESTRICT_EPS) P.teps[o] = sv;
+            else P.tv[o] = sv;
+            if (FAS) P.tf[o] = sr;
+        }
     }
 }
 
 // --------------------------------------------------------- FAS right side
-// On parent blocks after the restriction and the ghost fill of their level:
-// v_old = v (ghosts included) and f = R(r) + L v (eq. coarse-rhs).
+// On parent blocks, after the restriction (which also refreshed their ghosts):
+// v_old = v (ghosts included) and f = R(r) + L v (eq. coarse-rhs).  Several
+// workgroups per block, one cell or ghost per thread.
 template <typename T, int D, int BS, bool VAR>
 __global__ void __launch_bounds__(256) k_fas(Plane<T> P, DevTables tb, int lev, const int32_t *list,
-                                             uint64_t mask) {
+                                             uint64_t mask, int wg_per_block) {
     using g = G<D, BS>;
-    const int64_t b = list[blockIdx.x];
+    const int64_t b = list[blockIdx.x / wg_per_block];
     const int dm = tb.dom[b];
     if (!((mask >> dm) & 1)) return;
-    const Spacing s = spacing(tb, dm, lev);
-    for (int t = threadIdx.x; t < g::NC; t += blockDim.x) {
+    const int t = (blockIdx.x % wg_per_block) * blockDim.x + threadIdx.x;
+    if (t < g::NC) {
+        const Spacing s = spacing(tb, dm, lev);
         int i, j, k;
         g::decode(t, i, j, k);
         Stencil<T, D, BS, VAR> st;
         st.load(P, b, i, j, k, s, true);
         P.vold[b * g::NC + t] = st.vc;
         P.f[b * g::NC + t] += st.Lv();
+    } else if (t < g::NC + g::NG) {
+        P.voldg[b * g::NG + t - g::NC] = P.vg[b * g::NG + t - g::NC];
     }
-    for (int t = threadIdx.x; t < g::NG; t += blockDim.x) P.voldg[b * g::NG + t] = P.vg[b * g::NG + t];
 }
 
 // ------------------------------------------------- prolongation + correction
 // v^h += P(v^H - v_old^H) (eq. coarse-corr) with the nearest-neighbour interpolation
 // of eq. interp_2d / interp_3d: 2D (2 d_p + d_x + d_y)/4, 3D (d_p + d_x + d_y + d_z)/4,
 // the neighbours taken on the side of the fine cell (coarse ghosts near block faces).
+// One workgroup per fine block: d = v - v_old on the parent's octant and its face
+// halo is staged in LDS; the fine block is updated with unit stride and its boundary
+// values pushed into the mirroring ghosts.
 template <typename T, int D, int BS>
-__global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int b0, uint64_t mask,
-                                                 int wg_per_block, int nt) {
+__global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int lev, int b0, uint64_t mask,
+                                                 int nt) {
     using g = G<D, BS>;
-    const int64_t b = b0 + blockIdx.x / wg_per_block;
+    constexpr int HB = BS / 2, HP = HB + 2;
+    constexpr int NBOX = D == 3 ? HP * HP * HP : HP * HP;
+    constexpr int TPB = g::NC < 256 ? g::NC : 256;
+    __shared__ T s_d[NBOX];
+    const int64_t b = b0 + blockIdx.x;
     const int dm = tb.dom[b];
     if (!((mask >> dm) & 1)) return;
-    const int t = (blockIdx.x % wg_per_block) * blockDim.x + threadIdx.x;
-    if (t >= g::NC) return;
-    int i, j, k;
-    g::decode(t, i, j, k);
-    int gl[3] = {tb.org[3 * b] + i, tb.org[3 * b + 1] + j, D == 3 ? tb.org[3 * b + 2] + k : 0};
-    int pc[3], sg[3];
-    for (int a = 0; a < 3; a++) {
-        pc[a] = gl[a] >> 1;
-        sg[a] = (gl[a] & 1) ? 1 : -1;
-    }
+    const int tid = threadIdx.x;
     const int64_t p = tb.parent[b];
-    T d[4];
-    if (p >= 0) {
-        int l[3] = {pc[0] - tb.org[3 * p], pc[1] - tb.org[3 * p + 1], D == 3 ? pc[2] - tb.org[3 * p + 2] : 0};
-        d[0] = ld<D, BS>(P.v, P.vg, p, l[0], l[1], l[2]) - ld<D, BS>(P.vold, P.voldg, p, l[0], l[1], l[2]);
+    const int gc0[3] = {tb.org[3 * b] >> 1, tb.org[3 * b + 1] >> 1, D == 3 ? tb.org[3 * b + 2] >> 1 : 0};
+    int po[3] = {0, 0, 0};
+    if (p >= 0)
+        for (int a = 0; a < D; a++) po[a] = gc0[a] - tb.org[3 * p + a];
+    constexpr int ITB = (NBOX + TPB - 1) / TPB;
+    constexpr int IT = (g::NC + TPB - 1) / TPB;
+    const TailGeo tg = tail_geo(tb, dm, nt - 1, D);
+    // issue all loads first: the fine values this thread updates, then the staged box
+    T vr[IT];
 #pragma unroll
-        for (int a = 0; a < D; a++) {
-            int q[3] = {l[0], l[1], l[2]};
-            q[a] += sg[a];
-            d[1 + a] = ld<D, BS>(P.v, P.vg, p, q[0], q[1], q[2]) - ld<D, BS>(P.vold, P.voldg, p, q[0], q[1], q[2]);
-        }
-    } else {
-        TailGeo tg = tail_geo(tb, dm, nt - 1, D);
-        int64_t o = tg.idx(pc[0], pc[1], pc[2], D);
-        d[0] = P.tv[o] - P.tvold[o];
-#pragma unroll
-        for (int a = 0; a < D; a++) {
-            int q[3] = {pc[0], pc[1], pc[2]};
-            q[a] += sg[a];
-            int64_t oq = tg.idx(q[0], q[1], q[2], D);
-            d[1 + a] = P.tv[oq] - P.tvold[oq];
-        }
+    for (int m = 0; m < IT; m++) {
+        const int t = tid + m * TPB;
+        vr[m] = P.v[b * g::NC + (g::NC % TPB == 0 || t < g::NC ? t : 0)];
     }
-    T corr;
-    if (D == 2) corr = T(0.25) * (T(2) * d[0] + d[1] + d[2]);
-    else corr = T(0.25) * (d[0] + d[1] + d[2] + d[3]);
-    P.v[b * g::NC + t] += corr;
+    // box cell -> addresses of v and v_old (edges and corners of the halo, never
+    // used, read the box centre instead)
+    T av[ITB], ao[ITB];
+#pragma unroll
+    for (int m = 0; m < ITB; m++) {
+        int q = tid + m * TPB;
+        if (NBOX % TPB != 0 && q >= NBOX) q = 0;
+        int x = q % HP, y = (q / HP) % HP, z = D == 3 ? q / (HP * HP) : 1;
+        const int out = (x == 0 || x == HP - 1) + (y == 0 || y == HP - 1) + (D == 3 && (z == 0 || z == HP - 1));
+        if (out > 1) { x = 1; y = 1; z = 1; }
+        const int c[3] = {x - 1, y - 1, D == 3 ? z - 1 : 0};
+        const T *pv, *pvo;
+        if (p >= 0) {
+            const int l0 = po[0] + c[0], l1 = po[1] + c[1], l2 = po[2] + c[2];
+            pv = ldp<D, BS>(P.v, P.vg, p, l0, l1, l2);
+            pvo = ldp<D, BS>(P.vold, P.voldg, p, l0, l1, l2);
+        } else {
+            const int64_t o = tg.idx(gc0[0] + c[0], gc0[1] + c[1], gc0[2] + c[2], D);
+            pv = P.tv + o;
+            pvo = P.tvold + o;
+        }
+        av[m] = *pv;
+        ao[m] = *pvo;
+    }
+    T dv[ITB];
+#pragma unroll
+    for (int m = 0; m < ITB; m++) dv[m] = av[m] - ao[m];
+#pragma unroll
+    for (int m = 0; m < ITB; m++) {
+        const int q = tid + m * TPB;
+        if (q < NBOX) s_d[q] = dv[m];
+    }
+    __syncthreads();
+    const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
+#pragma unroll
+    for (int m = 0; m < IT; m++) {
+        const int t = tid + m * TPB;
+        if (g::NC % TPB != 0 && t >= g::NC) break;
+        int i, j, k;
+        g::decode(t, i, j, k);
+        const int x = (i >> 1) + 1, y = (j >> 1) + 1, z = D == 3 ? (k >> 1) + 1 : 0;
+        const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+        const int c0 = (z * HP + y) * HP + x;
+        const T d0 = s_d[c0], dx = s_d[c0 + sx], dy = s_d[c0 + sy * HP];
+        T corr;
+        if (D == 2) corr = T(0.25) * (T(2) * d0 + dx + dy);
+        else corr = T(0.25) * (d0 + dx + dy + s_d[c0 + sz * HP * HP]);
+        const T nv = vr[m] + corr;
+        P.v[b * g::NC + t] = nv;
+        push_ghosts<T, D, BS>(P.vg, tb, b, dm, hh, i, j, k, nv);
+    }
 }
 
 // --------------------------------------------------------------- the tail
@@ -408,33 +644,42 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int b
 // single process).  They are uniform grids, so each is stored whole with one ghost
 // layer; blocked red-black Gauss-Seidel with ghost refresh after each colour equals a
 // sweep over the whole grid.
+// Geometry of one tail grid and the domain's boundary data, cached in LDS.
+struct TailLev {
+    TailGeo g;            // cells per axis and offset relative to the domain's first tail array
+    double h[3], ih2[3];
+};
+struct TailBC {
+    int kind[6];
+    double value[6];
+};
+
 template <typename T, int D, bool VAR>
 struct Tail {
-    const Plane<T> &P;
-    const DevTables &tb;
-    int dm;
-    int nt;
-    double *red;   // shared reduction scratch
+    const TailLev *lv;         // [nt] in LDS
+    const TailBC *bc;          // in LDS
+    double *red;               // shared reduction scratch, one slot per wave
+    T *tv, *tvold, *tf, *teps; // this domain's tail arrays (global memory or LDS)
 
-    __device__ TailGeo geo(int lev) const { return tail_geo(tb, dm, lev, D); }
-    __device__ int64_t count(const TailGeo &g) const { return (int64_t)g.n[0] * g.n[1] * g.n[2]; }
-    __device__ void cell(const TailGeo &g, int64_t c, int &i, int &j, int &k) const {
-        i = (int)(c % g.n[0]);
-        j = (int)((c / g.n[0]) % g.n[1]);
-        k = (int)(c / ((int64_t)g.n[0] * g.n[1]));
+    __device__ __forceinline__ const TailGeo &geo(int lev) const { return lv[lev].g; }
+    __device__ __forceinline__ int count(const TailGeo &g) const { return g.n[0] * g.n[1] * g.n[2]; }
+    __device__ __forceinline__ void cell(const TailGeo &g, int c, int &i, int &j, int &k) const {
+        i = c % g.n[0];
+        const int r = c / g.n[0];
+        j = r % g.n[1];
+        k = r / g.n[1];
     }
 
     // Ghost layer of one tail grid (faces only): periodic copy or boundary condition.
     __device__ void ghosts(int lev, T *u, bool eps) const {
-        TailGeo g = geo(lev);
-        const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
+        const TailGeo &g = geo(lev);
         for (int a = 0; a < D; a++) {
-            int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
-            int n1 = g.n[t1], n2 = D == 3 ? g.n[t2] : 1;
-            int64_t tot = 2 * (int64_t)n1 * n2;
-            for (int64_t q = threadIdx.x; q < tot; q += blockDim.x) {
-                int side = (int)(q / ((int64_t)n1 * n2));
-                int r = (int)(q % ((int64_t)n1 * n2));
+            const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+            const int n1 = g.n[t1], n2 = D == 3 ? g.n[t2] : 1;
+            const int tot = 2 * n1 * n2;
+            for (int q = threadIdx.x; q < tot; q += blockDim.x) {
+                const int side = q / (n1 * n2);
+                const int r = q % (n1 * n2);
                 int c[3], in[3], op[3];
                 c[t1] = r % n1; c[t2] = D == 3 ? r / n1 : 0;
                 in[t1] = c[t1]; in[t2] = c[t2]; op[t1] = c[t1]; op[t2] = c[t2];
@@ -442,29 +687,28 @@ struct Tail {
                 in[a] = side ? g.n[a] - 1 : 0;
                 op[a] = side ? 0 : g.n[a] - 1;
                 if (D == 2) { c[2] = 0; in[2] = 0; op[2] = 0; }
-                int f = 2 * a + side;
-                int kind = tb.bck[6 * dm + f];
+                const int f = 2 * a + side;
+                const int kind = bc->kind[f];
                 T val;
                 if (kind == MG_BC_PERIODIC) val = u[g.idx(op[0], op[1], op[2], D)];
                 else if (eps) val = u[g.idx(in[0], in[1], in[2], D)];
-                else val = bc_ghost<T>(kind, tb.bcv[6 * dm + f], hh[a], side, u[g.idx(in[0], in[1], in[2], D)]);
+                else val = bc_ghost<T>(kind, bc->value[f], lv[lev].h[a], side, u[g.idx(in[0], in[1], in[2], D)]);
                 u[g.idx(c[0], c[1], c[2], D)] = val;
             }
         }
     }
 
-    __device__ void weights(int lev, const TailGeo &g, int i, int j, int k, T *w) const {
-        const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
+    __device__ __forceinline__ void weights(int lev, const TailGeo &g, int i, int j, int k, T *w) const {
         if (!VAR) {
-            for (int f = 0; f < 2 * D; f++) w[f] = T(1.0 / (hh[f / 2] * hh[f / 2]));
+            for (int f = 0; f < 2 * D; f++) w[f] = T(lv[lev].ih2[f / 2]);
         } else {
-            T e0 = P.teps[g.idx(i, j, k, D)];
-            int o[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k}, {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+            const T e0 = teps[g.idx(i, j, k, D)];
+            const int o[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k}, {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
             for (int f = 0; f < 2 * D; f++)
-                w[f] = harm(e0, P.teps[g.idx(o[f][0], o[f][1], o[f][2], D)]) * T(1.0 / (hh[f / 2] * hh[f / 2]));
+                w[f] = harm(e0, teps[g.idx(o[f][0], o[f][1], o[f][2], D)]) * T(lv[lev].ih2[f / 2]);
         }
     }
-    __device__ void nbrs(const TailGeo &g, const T *u, int i, int j, int k, T *nb) const {
+    __device__ __forceinline__ void nbrs(const TailGeo &g, const T *u, int i, int j, int k, T *nb) const {
         nb[0] = u[g.idx(i - 1, j, k, D)];
         nb[1] = u[g.idx(i + 1, j, k, D)];
         nb[2] = u[g.idx(i, j - 1, k, D)];
@@ -474,75 +718,74 @@ struct Tail {
             nb[5] = u[g.idx(i, j, k + 1, D)];
         }
     }
-    __device__ T Lv(int lev, const TailGeo &g, int i, int j, int k) const {
+    __device__ __forceinline__ T Lv(int lev, const TailGeo &g, int i, int j, int k) const {
         T w[6], nb[6];
         weights(lev, g, i, j, k, w);
-        nbrs(g, P.tv, i, j, k, nb);
-        T vc = P.tv[g.idx(i, j, k, D)], s = T(0);
+        nbrs(g, tv, i, j, k, nb);
+        const T vc = tv[g.idx(i, j, k, D)];
+        T s = T(0);
         for (int f = 0; f < 2 * D; f++) s += w[f] * (nb[f] - vc);
         return s;
     }
 
     __device__ void smooth(int lev) const {
-        TailGeo g = geo(lev);
-        int64_t n = count(g);
+        const TailGeo &g = geo(lev);
+        const int n = count(g);
         for (int colour = 0; colour < 2; colour++) {
-            for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
+            for (int c = threadIdx.x; c < n; c += blockDim.x) {
                 int i, j, k;
                 cell(g, c, i, j, k);
                 if (((i + j + k) & 1) != colour) continue;
                 T w[6], nb[6];
                 weights(lev, g, i, j, k, w);
-                nbrs(g, P.tv, i, j, k, nb);
+                nbrs(g, tv, i, j, k, nb);
                 T num = T(0), den = T(0);
                 for (int f = 0; f < 2 * D; f++) {
                     num += w[f] * nb[f];
                     den += w[f];
                 }
-                int64_t o = g.idx(i, j, k, D);
-                P.tv[o] = (num - P.tf[o]) / den;
+                const int64_t o = g.idx(i, j, k, D);
+                tv[o] = (num - tf[o]) / den;
             }
             __syncthreads();
-            ghosts(lev, P.tv, false);
+            ghosts(lev, tv, false);
             __syncthreads();
         }
     }
 
-    // Block-wide reductions (all threads get the result).
+    // Block-wide reductions (all threads get the result): wave shuffles, then one
+    // exchange through LDS.
     __device__ double reduce_max(double x) const {
-        red[threadIdx.x] = x;
-        __syncthreads();
-        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s) {
-                double o = red[threadIdx.x + s];
-                if (o > red[threadIdx.x] || o != o) red[threadIdx.x] = o;
-            }
-            __syncthreads();
+        for (int o = 32; o > 0; o >>= 1) {
+            double y = __shfl_xor(x, o);
+            if (y > x || y != y) x = y;
         }
-        double r = red[0];
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
         __syncthreads();
-        return r;
+        x = red[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++)
+            if (red[w] > x || red[w] != red[w]) x = red[w];
+        __syncthreads();
+        return x;
     }
     __device__ double reduce_sum(double x) const {
-        red[threadIdx.x] = x;
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
         __syncthreads();
-        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-            __syncthreads();
-        }
-        double r = red[0];
+        x = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) x += red[w];
         __syncthreads();
-        return r;
+        return x;
     }
 
     __device__ double resmax(int lev) const {
-        TailGeo g = geo(lev);
-        int64_t n = count(g);
+        const TailGeo &g = geo(lev);
+        const int n = count(g);
         double m = 0.0;
-        for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
             int i, j, k;
             cell(g, c, i, j, k);
-            double r = fabs((double)(P.tf[g.idx(i, j, k, D)] - Lv(lev, g, i, j, k)));
+            const double r = fabs((double)(tf[g.idx(i, j, k, D)] - Lv(lev, g, i, j, k)));
             if (r > m || r != r) m = r;
         }
         return reduce_max(m);
@@ -550,63 +793,64 @@ struct Tail {
 
     // Restriction lev -> lev-1 with the FAS right-hand side (as for block levels).
     __device__ void restrict_fas(int lev) const {
-        TailGeo gf = geo(lev), gc = geo(lev - 1);
-        int64_t n = count(gc);
-        for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
+        const TailGeo &gf = geo(lev), &gc = geo(lev - 1);
+        const int n = count(gc);
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
             int I, J, K;
             cell(gc, c, I, J, K);
             T sv = T(0), sr = T(0);
             for (int q = 0; q < (1 << D); q++) {
-                int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = D == 3 ? 2 * K + (q >> 2) : 0;
-                int64_t o = gf.idx(i, j, k, D);
-                sv += P.tv[o];
-                sr += P.tf[o] - Lv(lev, gf, i, j, k);
+                const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = D == 3 ? 2 * K + (q >> 2) : 0;
+                const int64_t o = gf.idx(i, j, k, D);
+                sv += tv[o];
+                sr += tf[o] - Lv(lev, gf, i, j, k);
             }
             const T inv = T(1) / T(1 << D);
-            int64_t oc = gc.idx(I, J, K, D);
-            P.tv[oc] = sv * inv;
-            P.tf[oc] = sr * inv;
+            const int64_t oc = gc.idx(I, J, K, D);
+            tv[oc] = sv * inv;
+            tf[oc] = sr * inv;
         }
         __syncthreads();
         finish_fas(lev - 1);
     }
     // Ghosts, v_old = v (ghosts included), f = R(r) + L v on one tail grid.
     __device__ void finish_fas(int lev) const {
-        ghosts(lev, P.tv, false);
+        ghosts(lev, tv, false);
         __syncthreads();
-        TailGeo g = geo(lev);
-        int64_t np = (int64_t)(g.n[0] + 2) * (g.n[1] + 2) * (D == 3 ? g.n[2] + 2 : 1);
-        for (int64_t c = threadIdx.x; c < np; c += blockDim.x) P.tvold[g.off + c] = P.tv[g.off + c];
-        int64_t n = count(g);
-        for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
+        const TailGeo &g = geo(lev);
+        const int np = (g.n[0] + 2) * (g.n[1] + 2) * (D == 3 ? g.n[2] + 2 : 1);
+        for (int c = threadIdx.x; c < np; c += blockDim.x) tvold[g.off + c] = tv[g.off + c];
+        const int n = count(g);
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
             int i, j, k;
             cell(g, c, i, j, k);
-            P.tf[g.idx(i, j, k, D)] += Lv(lev, g, i, j, k);
+            tf[g.idx(i, j, k, D)] += Lv(lev, g, i, j, k);
         }
         __syncthreads();
     }
 
     __device__ void correct(int lev) const {
-        TailGeo gf = geo(lev), gc = geo(lev - 1);
-        int64_t n = count(gf);
-        for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
+        const TailGeo &gf = geo(lev), &gc = geo(lev - 1);
+        const int n = count(gf);
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
             int i, j, k;
             cell(gf, c, i, j, k);
-            int p[3] = {i >> 1, j >> 1, k >> 1};
-            int sg[3] = {(i & 1) ? 1 : -1, (j & 1) ? 1 : -1, (k & 1) ? 1 : -1};
-            int64_t o = gc.idx(p[0], p[1], p[2], D);
-            T d0 = P.tv[o] - P.tvold[o], dn[3];
+            const int p[3] = {i >> 1, j >> 1, k >> 1};
+            const int sg[3] = {(i & 1) ? 1 : -1, (j & 1) ? 1 : -1, (k & 1) ? 1 : -1};
+            const int64_t o = gc.idx(p[0], p[1], p[2], D);
+            const T d0 = tv[o] - tvold[o];
+            T dn[3];
             for (int a = 0; a < D; a++) {
                 int q[3] = {p[0], p[1], p[2]};
                 q[a] += sg[a];
-                int64_t oq = gc.idx(q[0], q[1], q[2], D);
-                dn[a] = P.tv[oq] - P.tvold[oq];
+                const int64_t oq = gc.idx(q[0], q[1], q[2], D);
+                dn[a] = tv[oq] - tvold[oq];
             }
-            T corr = D == 2 ? T(0.25) * (T(2) * d0 + dn[0] + dn[1]) : T(0.25) * (d0 + dn[0] + dn[1] + dn[2]);
-            P.tv[gf.idx(i, j, k, D)] += corr;
+            const T corr = D == 2 ? T(0.25) * (T(2) * d0 + dn[0] + dn[1]) : T(0.25) * (d0 + dn[0] + dn[1] + dn[2]);
+            tv[gf.idx(i, j, k, D)] += corr;
         }
         __syncthreads();
-        ghosts(lev, P.tv, false);
+        ghosts(lev, tv, false);
         __syncthreads();
     }
 
@@ -616,31 +860,32 @@ struct Tail {
     // alternation of a one-cell Dirichlet grid).  Fully periodic: remove the mean of
     // f first.
     __device__ int coarse_solve(const TailParams &tp) const {
-        TailGeo g = geo(0);
-        int64_t n = count(g);
+        const TailGeo &g = geo(0);
+        const int n = count(g);
         bool per = true;
-        for (int f = 0; f < 2 * D; f++) per = per && tb.bck[6 * dm + f] == MG_BC_PERIODIC;
+        for (int f = 0; f < 2 * D; f++) per = per && bc->kind[f] == MG_BC_PERIODIC;
         if (per) {
             double s = 0.0;
-            for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
+            for (int c = threadIdx.x; c < n; c += blockDim.x) {
                 int i, j, k;
                 cell(g, c, i, j, k);
-                s += (double)P.tf[g.idx(i, j, k, D)];
+                s += (double)tf[g.idx(i, j, k, D)];
             }
-            double mean = reduce_sum(s) / (double)n;
-            for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
+            const double mean = reduce_sum(s) / (double)n;
+            for (int c = threadIdx.x; c < n; c += blockDim.x) {
                 int i, j, k;
                 cell(g, c, i, j, k);
-                P.tf[g.idx(i, j, k, D)] -= T(mean);
+                tf[g.idx(i, j, k, D)] -= T(mean);
             }
             __syncthreads();
         }
-        double r0 = resmax(0), rprev = r0;
-        double target = fmax(tp.abs_tol, tp.rel_tol * r0);
+        const double r0 = resmax(0);
+        double rprev = r0;
+        const double target = fmax(tp.abs_tol, tp.rel_tol * r0);
         int k;
         for (k = 1; k <= tp.n_max; k++) {
             smooth(0);
-            double r = resmax(0);
+            const double r = resmax(0);
             if (r <= target) break;
             if (k >= 2 && r > kStall * rprev) break;
             rprev = r;
@@ -653,7 +898,7 @@ struct Tail {
             for (int s = 0; s < tp.n_down; s++) smooth(l);
             restrict_fas(l);
         }
-        int steps = coarse_solve(tp);
+        const int steps = coarse_solve(tp);
         for (int l = 1; l <= top; l++) {
             correct(l);
             for (int s = 0; s < tp.n_up; s++) smooth(l);
@@ -662,13 +907,63 @@ struct Tail {
     }
 };
 
+// Padded cells of all tail grids of domain dm (levels 0..nt-1 are stored in order).
+__device__ __forceinline__ int64_t tail_span(const DevTables &tb, int dm, int nt, int dim, int64_t *first) {
+    *first = tb.tail_off[(size_t)dm * MAXLEV];
+    const int32_t *nc = tb.ncell + ((size_t)dm * MAXLEV + nt - 1) * 3;
+    int64_t last = (int64_t)(nc[0] + 2) * (nc[1] + 2) * (dim == 3 ? nc[2] + 2 : 1);
+    return tb.tail_off[(size_t)dm * MAXLEV + nt - 1] + last - *first;
+}
+
+// Caches the tail geometry of domain dm (offsets relative to its first tail array)
+// and its boundary data in LDS.
+__device__ void tail_setup(const DevTables &tb, int dm, int nt, int dim, int64_t first, TailLev *lv, TailBC *bc) {
+    if (threadIdx.x < nt) {
+        const int l = threadIdx.x;
+        TailGeo g = tail_geo(tb, dm, l, dim);
+        g.off -= first;
+        lv[l].g = g;
+        const double *h = tb.h + ((size_t)dm * MAXLEV + l) * 3;
+        for (int a = 0; a < 3; a++) {
+            lv[l].h[a] = h[a];
+            lv[l].ih2[a] = 1.0 / (h[a] * h[a]);
+        }
+    }
+    if (threadIdx.x < 6) {
+        bc->kind[threadIdx.x] = tb.bck[6 * dm + threadIdx.x];
+        bc->value[threadIdx.x] = tb.bcv[6 * dm + threadIdx.x];
+    }
+}
+
+// One workgroup per domain.  When the domain's tail grids fit in the dynamic LDS
+// allocation they are copied in, cycled there, and copied back.
 template <typename T, int D, bool VAR>
-__global__ void __launch_bounds__(1024) k_tail(Plane<T> P, DevTables tb, int nt, int mode, uint64_t mask,
-                                               TailParams tp, int32_t *steps_out) {
-    __shared__ double red[1024];
+__global__ void __launch_bounds__(512) k_tail(Plane<T> P, DevTables tb, int nt, int mode, uint64_t mask,
+                                              TailParams tp, int32_t *steps_out, int lds_bytes) {
+    extern __shared__ double smem[];
+    __shared__ double red[16];
+    __shared__ TailLev lvs[MAXLEV];
+    __shared__ TailBC bcs;
     const int dm = blockIdx.x;
     if (!((mask >> dm) & 1)) return;
-    Tail<T, D, VAR> tl{P, tb, dm, nt, red};
+    int64_t first;
+    const int64_t n = tail_span(tb, dm, nt, D, &first);
+    tail_setup(tb, dm, nt, D, first, lvs, &bcs);
+    const int nf = VAR ? 4 : 3;
+    const bool lds = n * nf * (int64_t)sizeof(T) <= lds_bytes;
+    Tail<T, D, VAR> tl{lvs, &bcs, red, P.tv + first, P.tvold + first, P.tf + first, VAR ? P.teps + first : nullptr};
+    if (lds) {
+        T *s = reinterpret_cast<T *>(smem);
+        for (int q = threadIdx.x; q < (int)n; q += blockDim.x) {
+            s[q] = tl.tv[q];
+            s[n + q] = tl.tvold[q];
+            s[2 * n + q] = tl.tf[q];
+            if (VAR) s[3 * n + q] = tl.teps[q];
+        }
+        tl.tv = s; tl.tvold = s + n; tl.tf = s + 2 * n;
+        if (VAR) tl.teps = s + 3 * n;
+    }
+    __syncthreads();
     const int top = nt - 1;
     // The restriction from the lowest block level left R(v) in v and R(r) in f.
     tl.finish_fas(top);
@@ -683,30 +978,44 @@ __global__ void __launch_bounds__(1024) k_tail(Plane<T> P, DevTables tb, int nt,
             steps = tl.vcycle(l, tp);
         }
     }
+    if (lds) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < (int)n; q += blockDim.x) {
+            P.tv[first + q] = tl.tv[q];
+            P.tvold[first + q] = tl.tvold[q];
+            P.tf[first + q] = tl.tf[q];
+        }
+    }
     if (threadIdx.x == 0) steps_out[dm] = steps;
 }
 
 // eps on the tail grids: restrict down from the top tail grid, then ghost layers.
 template <typename T, int D>
-__global__ void __launch_bounds__(1024) k_tail_eps(Plane<T> P, DevTables tb, int nt) {
-    __shared__ double red[1024];
+__global__ void __launch_bounds__(512) k_tail_eps(Plane<T> P, DevTables tb, int nt) {
+    __shared__ double red[16];
+    __shared__ TailLev lvs[MAXLEV];
+    __shared__ TailBC bcs;
     const int dm = blockIdx.x;
-    Tail<T, D, true> tl{P, tb, dm, nt, red};
+    int64_t first;
+    tail_span(tb, dm, nt, D, &first);
+    tail_setup(tb, dm, nt, D, first, lvs, &bcs);
+    __syncthreads();
+    Tail<T, D, true> tl{lvs, &bcs, red, P.tv + first, P.tvold + first, P.tf + first, P.teps + first};
     for (int l = nt - 1; l >= 1; l--) {
-        TailGeo gf = tl.geo(l), gc = tl.geo(l - 1);
-        int64_t n = tl.count(gc);
-        for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
+        const TailGeo &gf = tl.geo(l), &gc = tl.geo(l - 1);
+        const int n = tl.count(gc);
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
             int I, J, K;
             tl.cell(gc, c, I, J, K);
             T s = T(0);
             for (int q = 0; q < (1 << D); q++)
-                s += P.teps[gf.idx(2 * I + (q & 1), 2 * J + ((q >> 1) & 1), D == 3 ? 2 * K + (q >> 2) : 0, D)];
-            P.teps[gc.idx(I, J, K, D)] = s / T(1 << D);
+                s += tl.teps[gf.idx(2 * I + (q & 1), 2 * J + ((q >> 1) & 1), D == 3 ? 2 * K + (q >> 2) : 0, D)];
+            tl.teps[gc.idx(I, J, K, D)] = s / T(1 << D);
         }
         __syncthreads();
     }
     for (int l = 0; l < nt; l++) {
-        tl.ghosts(l, P.teps, true);
+        tl.ghosts(l, tl.teps, true);
         __syncthreads();
     }
 }
@@ -734,48 +1043,111 @@ __global__ void __launch_bounds__(256) k_scatter(T *blk, double *user, DevTables
 }
 
 // ------------------------------------------------------------------ norms
+// Workgroup-wide sum and max (wave shuffles, then one LDS exchange).
+template <int TPB>
+__device__ __forceinline__ void block_reduce4(double &mr, double &sr, double &mf, double &sf) {
+    __shared__ double red[4][TPB / 64];
+    for (int o = 32; o > 0; o >>= 1) {
+        double a = __shfl_xor(mr, o), b = __shfl_xor(sr, o), c = __shfl_xor(mf, o), d = __shfl_xor(sf, o);
+        if (a > mr || a != a) mr = a;
+        sr += b;
+        mf = fmax(mf, c);
+        sf += d;
+    }
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = mr; red[1][w] = sr; red[2][w] = mf; red[3][w] = sf;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < TPB / 64; q++) {
+            if (red[0][q] > mr || red[0][q] != red[0][q]) mr = red[0][q];
+            sr += red[1][q];
+            mf = fmax(mf, red[2][q]);
+            sf += red[3][q];
+        }
+    }
+}
+
 // Composite residual r = f - L v on every leaf block (FP64), with per-block partial
 // max |r|, sum vol r^2, max |f|, sum vol f^2; optionally writes r into the leaf
 // blocks of an output field (the right-hand side of an FP32 correction solve).
+// One workgroup per leaf block, v with its ghosts staged in LDS.
 template <int D, int BS, bool VAR>
 __global__ void __launch_bounds__(256) k_norm(Plane<double> P, DevTables tb, double *partials,
                                               float *rout32, double *rout64) {
     using g = G<D, BS>;
-    __shared__ double sm[4][256];
+    constexpr int TPB = 256;
+    constexpr int IT = (g::NC + TPB - 1) / TPB;
+    __shared__ __align__(16) double s_v[g::NC + g::NG];
     const int rank = blockIdx.x;
     const int64_t b = tb.leaf_blk[rank];
     const int dm = tb.dom[b], lev = tb.lev[b];
-    const Spacing s = spacing(tb, dm, lev);
+    const int tid = threadIdx.x;
+    Stager<double, 1, g::NC, 0, TPB> st_v;
+    Stager<double, 1, g::NG, 0, TPB> st_g;
+    st_v.load(P.v + b * g::NC);
+    st_g.load(P.vg + b * g::NG);
+    double fr[IT];
+#pragma unroll
+    for (int m = 0; m < IT; m++) {
+        const int t = tid + m * TPB;
+        fr[m] = P.f[b * g::NC + (g::NC % TPB == 0 || t < g::NC ? t : 0)];
+    }
+    st_v.store(s_v);
+    st_g.store(s_v + g::NC);
+    __syncthreads();
     const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
+    double ih2[3];
+    for (int a = 0; a < 3; a++) ih2[a] = 1.0 / (hh[a] * hh[a]);
     const double vol = hh[0] * hh[1] * (D == 3 ? hh[2] : 1.0);
     double mr = 0, sr = 0, mf = 0, sf = 0;
-    for (int t = threadIdx.x; t < g::NC; t += blockDim.x) {
+#pragma unroll
+    for (int m = 0; m < IT; m++) {
+        const int t = tid + m * TPB;
+        if (g::NC % TPB != 0 && t >= g::NC) break;
         int i, j, k;
         g::decode(t, i, j, k);
-        Stencil<double, D, BS, VAR> st;
-        st.load(P, b, i, j, k, s, true);
-        double f = P.f[b * g::NC + t];
-        double r = f - st.Lv();
+        const double vc = s_v[t];
+        double nb[6];
+        nb[0] = i > 0 ? s_v[g::in(i - 1, j, k)] : s_v[g::NC + g::gh(0, j, k)];
+        nb[1] = i < BS - 1 ? s_v[g::in(i + 1, j, k)] : s_v[g::NC + g::gh(1, j, k)];
+        nb[2] = j > 0 ? s_v[g::in(i, j - 1, k)] : s_v[g::NC + g::gh(2, i, k)];
+        nb[3] = j < BS - 1 ? s_v[g::in(i, j + 1, k)] : s_v[g::NC + g::gh(3, i, k)];
+        if (D == 3) {
+            nb[4] = k > 0 ? s_v[g::in(i, j, k - 1)] : s_v[g::NC + g::gh(4, i, j)];
+            nb[5] = k < BS - 1 ? s_v[g::in(i, j, k + 1)] : s_v[g::NC + g::gh(5, i, j)];
+        }
+        double lv = 0.0;
+        if (!VAR) {
+            for (int f = 0; f < 2 * D; f++) lv += ih2[f >> 1] * (nb[f] - vc);
+        } else {
+            const double e0 = P.eps[b * g::NC + t];
+            double en[6];
+            en[0] = ld<D, BS>(P.eps, P.epsg, b, i - 1, j, k);
+            en[1] = ld<D, BS>(P.eps, P.epsg, b, i + 1, j, k);
+            en[2] = ld<D, BS>(P.eps, P.epsg, b, i, j - 1, k);
+            en[3] = ld<D, BS>(P.eps, P.epsg, b, i, j + 1, k);
+            if (D == 3) {
+                en[4] = ld<D, BS>(P.eps, P.epsg, b, i, j, k - 1);
+                en[5] = ld<D, BS>(P.eps, P.epsg, b, i, j, k + 1);
+            }
+            for (int f = 0; f < 2 * D; f++) lv += harm(e0, en[f]) * ih2[f >> 1] * (nb[f] - vc);
+        }
+        const double fv = fr[m];
+        const double r = fv - lv;
         if (fabs(r) > mr || r != r) mr = fabs(r);
-        if (fabs(f) > mf) mf = fabs(f);
+        if (fabs(fv) > mf) mf = fabs(fv);
         sr += vol * r * r;
-        sf += vol * f * f;
+        sf += vol * fv * fv;
         if (rout32) rout32[b * g::NC + t] = (float)r;
         if (rout64) rout64[b * g::NC + t] = r;
     }
-    sm[0][threadIdx.x] = mr; sm[1][threadIdx.x] = sr; sm[2][threadIdx.x] = mf; sm[3][threadIdx.x] = sf;
-    __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) {
-            double o = sm[0][threadIdx.x + st];
-            if (o > sm[0][threadIdx.x] || o != o) sm[0][threadIdx.x] = o;
-            sm[1][threadIdx.x] += sm[1][threadIdx.x + st];
-            sm[2][threadIdx.x] = fmax(sm[2][threadIdx.x], sm[2][threadIdx.x + st]);
-            sm[3][threadIdx.x] += sm[3][threadIdx.x + st];
-        }
-        __syncthreads();
+    block_reduce4<TPB>(mr, sr, mf, sf);
+    if (tid == 0) {
+        double *o = partials + 4 * (int64_t)rank;
+        o[0] = mr; o[1] = sr; o[2] = mf; o[3] = sf;
     }
-    if (threadIdx.x < 4) partials[4 * (int64_t)rank + threadIdx.x] = sm[threadIdx.x][0];
 }
 
 // Per-domain combination of the per-block partials (fixed order: deterministic).
@@ -806,12 +1178,22 @@ __global__ void __launch_bounds__(256) k_reduce_norms(DevTables tb, const double
     if (threadIdx.x < 4) out[4 * dm + threadIdx.x] = sm[threadIdx.x][0];
 }
 
-// v64 += v32 on every leaf block (the FP64 update of iterative refinement).
-template <int NC>
-__global__ void __launch_bounds__(256) k_add_leaf(double *v64, const float *v32, DevTables tb, int wg_per_block) {
+// v64 += v32 on every leaf block (the FP64 update of iterative refinement), with the
+// same-level and boundary ghosts of the FP64 field pushed.
+template <int D, int BS>
+__global__ void __launch_bounds__(256) k_add_leaf(double *v64, double *vg64, const float *v32, DevTables tb,
+                                                  int wg_per_block) {
+    using g = G<D, BS>;
     const int64_t b = tb.leaf_blk[blockIdx.x / wg_per_block];
     const int t = (blockIdx.x % wg_per_block) * blockDim.x + threadIdx.x;
-    if (t < NC) v64[b * NC + t] += (double)v32[b * NC + t];
+    if (t >= g::NC) return;
+    const int dm = tb.dom[b];
+    const double *hh = tb.h + ((size_t)dm * MAXLEV + tb.lev[b]) * 3;
+    const double nv = v64[b * g::NC + t] + (double)v32[b * g::NC + t];
+    v64[b * g::NC + t] = nv;
+    int i, j, k;
+    g::decode(t, i, j, k);
+    push_ghosts<double, D, BS>(vg64, tb, b, dm, hh, i, j, k, nv);
 }
 
 // dJ/deps per leaf cell from phi (v plane, ghosts filled) and lambda (blocks + ghosts).
@@ -875,10 +1257,8 @@ void K<T>::gsrb(const Launch &L, const Plane<T> &P, int lev, int b0, int nb, int
     DISPATCH_DB(L, {
         constexpr int NH = G<D, BS>::NH;
         constexpr int TPB = NH < 256 ? NH : 256;
-        constexpr int WPB = NH / TPB;
-        dim3 grid((unsigned)(nb * WPB));
-        if (var) k_gsrb<T, D, BS, true><<<grid, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask, WPB);
-        else k_gsrb<T, D, BS, false><<<grid, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask, WPB);
+        if (var) k_gsrb<T, D, BS, true><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+        else k_gsrb<T, D, BS, false><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
     });
 }
 
@@ -903,15 +1283,13 @@ void K<T>::restrict_down(const Launch &L, const Plane<T> &P, int lev, int b0, in
         constexpr int HB = BS / 2;
         constexpr int NQ = D == 3 ? HB * HB * HB : HB * HB;
         constexpr int TPB = NQ < 256 ? NQ : 256;
-        constexpr int WPB = NQ / TPB;
-        dim3 grid((unsigned)(nb * WPB));
         if (mode == RESTRICT_FAS) {
-            if (var) k_restrict<T, D, BS, true, RESTRICT_FAS><<<grid, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, WPB, L.nt);
-            else k_restrict<T, D, BS, false, RESTRICT_FAS><<<grid, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, WPB, L.nt);
+            if (var) k_restrict<T, D, BS, true, RESTRICT_FAS><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, L.nt);
+            else k_restrict<T, D, BS, false, RESTRICT_FAS><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, L.nt);
         } else if (mode == RESTRICT_V) {
-            k_restrict<T, D, BS, false, RESTRICT_V><<<grid, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, WPB, L.nt);
+            k_restrict<T, D, BS, false, RESTRICT_V><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, L.nt);
         } else {
-            k_restrict<T, D, BS, false, RESTRICT_EPS><<<grid, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, WPB, L.nt);
+            k_restrict<T, D, BS, false, RESTRICT_EPS><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, L.nt);
         }
     });
 }
@@ -921,32 +1299,33 @@ void K<T>::fas(const Launch &L, const Plane<T> &P, int lev, const int32_t *list,
                bool var) {
     if (nlist <= 0) return;
     DISPATCH_DB(L, {
-        if (var) k_fas<T, D, BS, true><<<nlist, 256, 0, L.stream>>>(P, L.tb, lev, list, mask);
-        else k_fas<T, D, BS, false><<<nlist, 256, 0, L.stream>>>(P, L.tb, lev, list, mask);
+        constexpr int N = G<D, BS>::NC + G<D, BS>::NG;
+        constexpr int WPB = (N + 255) / 256;
+        if (var) k_fas<T, D, BS, true><<<nlist * WPB, 256, 0, L.stream>>>(P, L.tb, lev, list, mask, WPB);
+        else k_fas<T, D, BS, false><<<nlist * WPB, 256, 0, L.stream>>>(P, L.tb, lev, list, mask, WPB);
     });
 }
 
 template <typename T>
 void K<T>::correct(const Launch &L, const Plane<T> &P, int lev, int b0, int nb, uint64_t mask) {
-    (void)lev;
     if (nb <= 0) return;
     DISPATCH_DB(L, {
         constexpr int NC = G<D, BS>::NC;
         constexpr int TPB = NC < 256 ? NC : 256;
-        constexpr int WPB = NC / TPB;
-        k_correct<T, D, BS><<<(unsigned)(nb * WPB), TPB, 0, L.stream>>>(P, L.tb, b0, mask, WPB, L.nt);
+        k_correct<T, D, BS><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, L.nt);
     });
 }
 
 template <typename T>
 void K<T>::tail(const Launch &L, const Plane<T> &P, int mode, uint64_t mask, const TailParams &tp, bool var) {
     const int TPB = 512;
+    const int lds = 60 * 1024;
     if (L.dim == 3) {
-        if (var) k_tail<T, 3, true><<<L.ndom, TPB, 0, L.stream>>>(P, L.tb, L.nt, mode, mask, tp, L.coarse_steps);
-        else k_tail<T, 3, false><<<L.ndom, TPB, 0, L.stream>>>(P, L.tb, L.nt, mode, mask, tp, L.coarse_steps);
+        if (var) k_tail<T, 3, true><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, L.nt, mode, mask, tp, L.coarse_steps, lds);
+        else k_tail<T, 3, false><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, L.nt, mode, mask, tp, L.coarse_steps, lds);
     } else {
-        if (var) k_tail<T, 2, true><<<L.ndom, TPB, 0, L.stream>>>(P, L.tb, L.nt, mode, mask, tp, L.coarse_steps);
-        else k_tail<T, 2, false><<<L.ndom, TPB, 0, L.stream>>>(P, L.tb, L.nt, mode, mask, tp, L.coarse_steps);
+        if (var) k_tail<T, 2, true><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, L.nt, mode, mask, tp, L.coarse_steps, lds);
+        else k_tail<T, 2, false><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, L.nt, mode, mask, tp, L.coarse_steps, lds);
     }
 }
 
@@ -1005,18 +1384,13 @@ void launch_reduce_norms(const Launch &L) {
     k_reduce_norms<<<L.ndom, 256, 0, L.stream>>>(L.tb, L.partials, L.dom_norms);
 }
 
-void launch_add_leaf(const Launch &L, double *v64, const float *v32, int nleafblk) {
+void launch_add_leaf(const Launch &L, double *v64, double *vg64, const float *v32, int nleafblk) {
     if (nleafblk <= 0) return;
-    const int nc = cells(L.dim, L.bs);
-    const int tpb = nc < 256 ? nc : 256, wpb = nc / tpb;
-    const unsigned grid = (unsigned)(nleafblk * wpb);
-    switch (nc) {
-        case 4096: k_add_leaf<4096><<<grid, tpb, 0, L.stream>>>(v64, v32, L.tb, wpb); break;
-        case 512: k_add_leaf<512><<<grid, tpb, 0, L.stream>>>(v64, v32, L.tb, wpb); break;
-        case 256: k_add_leaf<256><<<grid, tpb, 0, L.stream>>>(v64, v32, L.tb, wpb); break;
-        case 64: k_add_leaf<64><<<grid, tpb, 0, L.stream>>>(v64, v32, L.tb, wpb); break;
-        default: k_add_leaf<16><<<grid, tpb, 0, L.stream>>>(v64, v32, L.tb, wpb); break;
-    }
+    DISPATCH_DB(L, {
+        constexpr int NC = G<D, BS>::NC;
+        constexpr int TPB = NC < 256 ? NC : 256;
+        k_add_leaf<D, BS><<<(unsigned)(nleafblk * (NC / TPB)), TPB, 0, L.stream>>>(v64, vg64, v32, L.tb, NC / TPB);
+    });
 }
 
 void launch_face_gradient(const Launch &L, const Plane<double> &P, const double *lam, const double *lamg,
