@@ -38,6 +38,10 @@ def _args():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-mixed", action="store_true")
     p.add_argument("--cpu-sample-cycles", type=int, default=1, help="V-cycles after the FMG in the CPU sample")
+    p.add_argument("--workload", default="periodic256",
+                   choices=["periodic256", "dirichlet2d", "amr-literal", "amr-nested", "varcoef-nested", "batch"],
+                   help="periodic256 is the benchmark line; the others print report lines")
+    p.add_argument("--max-cycles", type=int, default=60)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     return p.parse_args()
@@ -87,17 +91,21 @@ def traffic_from_profile(n_cells):
     return d.get("bytes_per_launch")
 
 
+MAX_CYCLES = 60
+
+
 def run_solve(tree, f_dev, zero_dev, tol):
     tree.set_rhs(f_dev)
     tree.set_phi(zero_dev)
-    cycles, rc = tree.solve(rel_tol=tol, max_cycles=60, fmg_first=True, raise_on_fail=False)
+    cycles, rc = tree.solve(rel_tol=tol, max_cycles=MAX_CYCLES, fmg_first=True, raise_on_fail=False)
     return cycles, rc
 
 
-def timed(tree, f_dev, zero_dev, tol, steps, warmup, profile=False):
+def timed(tree, f_dev, zero_dev, tol, steps, warmup, profile=False, fn=None):
     import torch
+    fn = fn or (lambda: run_solve(tree, f_dev, zero_dev, tol))
     for _ in range(warmup):
-        run_solve(tree, f_dev, zero_dev, tol)
+        fn()
     torch.cuda.synchronize()
     if profile:
         tree.profile_enable(True)
@@ -105,7 +113,7 @@ def timed(tree, f_dev, zero_dev, tol, steps, warmup, profile=False):
     cyc = []
     rcs = []
     for _ in range(steps):
-        c, rc = run_solve(tree, f_dev, zero_dev, tol)
+        c, rc = fn()
         cyc.append(c)
         rcs.append(rc)
     torch.cuda.synchronize()
@@ -134,14 +142,123 @@ def cpu_baseline(w, sample_cycles):
                       f"({o.n_leaf} leaf cells), {dt:.2f} s on one host thread"}
 
 
+def _tree_of(w, precision, mg):
+    doms = [mg.Domain(d.dim, d.base_cells, d.lo, d.hi, d.bc_kind, list(d.bc_value)) for d in w.domains]
+    p = mg.default_params(precision=precision, variable_eps=1 if w.variable_eps else 0)
+    return mg.Tree(doms, bs=w.bs, max_refine=w.max_refine, refine=w.refine, params=p)
+
+
+def _inputs(w, t):
+    import numpy as np
+    import torch
+    lay = t.leaf_layout()
+    f = np.concatenate([w.rhs(i, lay[lay[:, 0] == i][:, 1:]) for i in range(len(w.domains))])
+    e = None
+    if w.variable_eps:
+        e = torch.from_numpy(np.concatenate([w.eps(i, lay[lay[:, 0] == i][:, 1:])
+                                             for i in range(len(w.domains))])).cuda()
+    return torch.from_numpy(f).cuda(), e, lay
+
+
+def report(a):
+    """Report lines for the other workloads (not the benchmark line)."""
+    import numpy as np
+    import torch
+    from paper_1901_11370_amd import mg
+    from paper_1901_11370_amd import workloads as W
+
+    base = {"n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "data": "synthetic", "unit": "cell-updates/s",
+            "higher_is_better": True}
+    if a.workload == "dirichlet2d":
+        w = W.config1()
+        t = _tree_of(w, mg.MG_FP64, mg)
+        f, _, _ = _inputs(w, t)
+        z = torch.zeros_like(f)
+
+        def ten():
+            t.set_rhs(f)
+            t.set_phi(z)
+            t.vcycle(10)
+            r, _ = t.residual_norm()
+            return 10, 0
+        dt, _, _, _ = timed(t, f, z, a.tol, a.steps, a.warmup, fn=ten)
+        out = dict(base, metric="time per 10 V(2,2) cycles", value=t.n_leaf * 10 / dt, ms_per_step=dt * 1e3,
+                   dtype="f64", config={"workload": "poisson2d_128^2_dirichlet_sine_10xV(2,2)", "leaf_cells": t.n_leaf},
+                   final_rel_residual=t.residual_norm()[0])
+        print(json.dumps(out), flush=True)
+        return
+    if a.workload in ("amr-literal", "amr-nested", "varcoef-nested"):
+        w = W.config3(nested=a.workload != "amr-literal") if a.workload != "varcoef-nested" else W.config4(nested=True)
+        out = dict(base, metric="time-to-1e-10 residual", config={"workload": w.name})
+        for prec, key in ((mg.MG_FP64, "fp64"), (mg.MG_MIXED, "mixed")):
+            t = _tree_of(w, prec, mg)
+            f, e, lay = _inputs(w, t)
+            if e is not None:
+                t.set_eps(e)
+            z = torch.zeros_like(f)
+            dt, cyc, rcs, _ = timed(t, f, z, a.tol, a.steps, a.warmup)
+            r, s_ = t.solve_stats()
+            out[key] = {"time_to_tol_ms": dt * 1e3, "cycles": cyc[-1], "converged": rcs[-1] == 0,
+                        "final_rel_residual": float(r[-1]), "value": t.n_leaf * cyc[-1] / dt,
+                        "history": [float(x) for x in r]}
+            out["config"]["leaf_cells"] = t.n_leaf
+            out["config"]["levels"] = t.num_levels()
+            if key == "fp64":
+                phi64 = t.get_phi()
+            else:
+                out[key]["rel_diff_vs_fp64_solution"] = float(np.abs(t.get_phi() - phi64).max() / np.abs(phi64).max())
+            del t
+            torch.cuda.empty_cache()
+        out["value"] = out["fp64"]["value"]
+        out["ms_per_step"] = out["fp64"]["time_to_tol_ms"]
+        out["dtype"] = "f64"
+        print(json.dumps(out), flush=True)
+        return
+    if a.workload == "batch":
+        from paper_1901_11370_amd.autograd import mg_solve
+        w = W.config5()
+        t = _tree_of(w, mg.MG_MIXED, mg)
+        f, e, lay = _inputs(w, t)
+        tgt = torch.from_numpy(np.concatenate([w.target(i, lay[lay[:, 0] == i][:, 1:])
+                                               for i in range(len(w.domains))])).cuda()
+
+        def fwd_bwd():
+            ff = f.clone().requires_grad_(True)
+            ee = e.clone().requires_grad_(True)
+            phi = mg_solve(ff, ee, t, a.tol, a.max_cycles)
+            J = 0.5 * torch.sum((phi - tgt) ** 2)
+            J.backward()
+            return 1, 0
+        t.set_eps(e)
+        t.set_rhs(f)
+        t.set_phi(torch.zeros_like(f))
+        t0 = time.perf_counter()
+        cyc, _ = t.solve(rel_tol=a.tol, max_cycles=a.max_cycles, raise_on_fail=False)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        fwd_res = [float(x) for x in t.domain_residual_norms()[0]]
+        dt, _, _, _ = timed(t, f, None, a.tol, a.steps, a.warmup, fn=fwd_bwd)
+        out = dict(base, metric="forward + adjoint backward time", value=t.n_leaf / dt, ms_per_step=dt * 1e3,
+                   dtype="f32 cycles in f64 refinement",
+                   config={"workload": w.name, "leaf_cells": t.n_leaf, "domains": len(w.domains)},
+                   forward_ir_steps=cyc, forward_ms=t_fwd * 1e3, forward_domain_residuals=fwd_res)
+        print(json.dumps(out), flush=True)
+        return
+
+
 def main():
     a = _args()
+    global MAX_CYCLES
+    MAX_CYCLES = a.max_cycles
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
               "(see DESIGN.md for how the solver would shard)", file=sys.stderr)
         sys.exit(2)
     if a.copy_calibration:
         copy_calibration(a.copy_calibration)
+        return
+    if a.workload != "periodic256":
+        report(a)
         return
     import numpy as np
     import torch

@@ -111,6 +111,7 @@ size_t plan(mg_tree *t, char *base) {
     size_t o_h = L.take<double>((size_t)T.ndom * MAXLEV * 3), o_nc = L.take<int32_t>((size_t)T.ndom * MAXLEV * 3);
     size_t o_bck = L.take<int32_t>(6 * T.ndom), o_bcv = L.take<double>(6 * T.ndom), o_bc0 = L.take<double>(6 * T.ndom);
     size_t o_toff = L.take<int64_t>((size_t)T.ndom * MAXLEV);
+    size_t o_ttop = L.take<int32_t>(T.ndom);
     std::vector<size_t> o_parl(T.nlev), o_cfl(T.nlev);
     for (int l = 0; l < T.nlev; l++) {
         o_parl[l] = L.take<int32_t>(T.parents_of_level[l].size());
@@ -144,6 +145,7 @@ size_t plan(mg_tree *t, char *base) {
         put(o_bcv, bcv.data(), bcv.size() * 8);
         put(o_bc0, bc0.data(), bc0.size() * 8);
         put(o_toff, T.tail_off.data(), T.tail_off.size() * 8);
+        put(o_ttop, T.tail_top.data(), T.tail_top.size() * 4);
         for (int l = 0; l < T.nlev; l++) {
             put(o_parl[l], T.parents_of_level[l].data(), T.parents_of_level[l].size() * 4);
             put(o_cfl[l], T.cf_of_level[l].data(), T.cf_of_level[l].size() * 4);
@@ -162,6 +164,7 @@ size_t plan(mg_tree *t, char *base) {
         tb.bck = (const int32_t *)P(o_bck);
         tb.bcv = (const double *)P(o_bcv);
         tb.tail_off = (const int64_t *)P(o_toff);
+        tb.tail_top = (const int32_t *)P(o_ttop);
         t->tb0 = tb;
         t->tb0.bcv = (const double *)P(o_bc0);
         t->d_parents.assign(T.nlev, nullptr);
@@ -290,13 +293,65 @@ struct Driver {
         K<T>::correct(L, P, l, lvb0(t, l), lvnb(t, l), m);
         cf_refresh(l, m);
     }
+    // ---- tail levels: the large ones (per domain) as multi-workgroup launches, the
+    // rest inside the one-workgroup kernel
+    UGrid ugrid(int dm, int l) const {
+        const HostTree &H = t->T;
+        UGrid g;
+        g.dm = dm;
+        g.lev = l;
+        for (int a = 0; a < 3; a++) {
+            g.n[a] = H.ncell[((size_t)dm * MAXLEV + l) * 3 + a];
+            g.h[a] = H.h[((size_t)dm * MAXLEV + l) * 3 + a];
+        }
+        g.off = H.tail_off[(size_t)dm * MAXLEV + l];
+        return g;
+    }
+    bool big(int dm, int l) const { return l < t->T.nt && l > t->T.tail_top[dm]; }
+    bool in(uint64_t m, int dm) const { return (m >> dm) & 1; }
+    // Ghosts, then v_old and the FAS right-hand side, of a large tail grid whose
+    // values a restriction just wrote.
+    void uenter(int dm, int l) {
+        const UGrid g = ugrid(dm, l);
+        K<T>::ughost(L, P, g);
+        K<T>::ufas(L, P, g, v);
+    }
+    void usmooth(int dm, int l, int steps) {
+        const UGrid g = ugrid(dm, l);
+        for (int s = 0; s < steps; s++)
+            for (int c = 0; c < 2; c++) K<T>::ugsrb(L, P, g, c, v);
+    }
+    // V-cycle over the tail levels <= top of the domains in m.
+    void tail_vcycle(int top, uint64_t m) {
+        for (int l = top; l >= 1; l--)
+            for (int dm = 0; dm < t->T.ndom; dm++) {
+                if (!in(m, dm) || !big(dm, l)) continue;
+                usmooth(dm, l, t->prm.n_down);
+                K<T>::urestrict(L, P, ugrid(dm, l), ugrid(dm, l - 1), v);
+                if (big(dm, l - 1)) uenter(dm, l - 1);
+            }
+        K<T>::tail(L, P, TAIL_VCYCLE, m, tail_params(t), v);
+        for (int l = 1; l <= top; l++)
+            for (int dm = 0; dm < t->T.ndom; dm++) {
+                if (!in(m, dm) || !big(dm, l)) continue;
+                K<T>::ucorrect(L, P, ugrid(dm, l), ugrid(dm, l - 1));
+                usmooth(dm, l, t->prm.n_up);
+            }
+    }
+    // The restriction from the lowest block level wrote the top tail grid.
+    void enter_tail(uint64_t m) {
+        for (int dm = 0; dm < t->T.ndom; dm++)
+            if (in(m, dm) && big(dm, t->T.nt - 1)) uenter(dm, t->T.nt - 1);
+    }
+
     void vcycle(int top, uint64_t m) {
         const int nt = t->T.nt;
         for (int l = top; l >= nt; l--) {
             smooth(l, m, t->prm.n_down);
             restrict_fas(l, m);
         }
-        K<T>::tail(L, P, TAIL_VCYCLE, m, tail_params(t), v);
+        enter_tail(m);
+        tail_vcycle(nt - 1, m);
         for (int l = nt; l <= top; l++) {
             correct(l, m);
             smooth(l, m, t->prm.n_up);
@@ -306,7 +361,23 @@ struct Driver {
         const int nt = t->T.nt, top = t->T.nlev - 1;
         const uint64_t all = all_mask(t);
         for (int l = top; l >= nt; l--) restrict_fas(l, all);
+        enter_tail(all);
+        for (int l = nt - 1; l >= 1; l--)
+            for (int dm = 0; dm < t->T.ndom; dm++) {
+                if (!big(dm, l)) continue;
+                K<T>::urestrict(L, P, ugrid(dm, l), ugrid(dm, l - 1), v);
+                if (big(dm, l - 1)) uenter(dm, l - 1);
+            }
         K<T>::tail(L, P, TAIL_FMG, all, tail_params(t), v);
+        for (int l = 1; l < nt; l++) {
+            uint64_t m = 0;
+            for (int dm = 0; dm < t->T.ndom; dm++)
+                if (big(dm, l)) {
+                    m |= 1ull << dm;
+                    K<T>::ucorrect(L, P, ugrid(dm, l), ugrid(dm, l - 1));
+                }
+            if (m) tail_vcycle(l, m);
+        }
         for (int l = nt; l <= top; l++) {
             uint64_t m = mask_top_at_least(t, l);
             correct(l, m);

@@ -33,6 +33,19 @@ struct DevTables {
     const int32_t *bck;       // [ndom][6] boundary kinds
     const double *bcv;        // [ndom][6] boundary values (or zeros: homogeneous)
     const int64_t *tail_off;  // [ndom][MAXLEV] offset of a tail level's padded array (cells)
+    const int32_t *tail_top;  // [ndom] highest tail level run by the one-workgroup kernel
+};
+
+// Tail levels with more cells than this (per domain) run as multi-workgroup launches;
+// the levels below run inside one workgroup.
+constexpr int kTailBig = 4096;
+
+// One uniform tail grid of one domain, passed by value.
+struct UGrid {
+    int dm, lev;
+    int n[3];
+    int64_t off;
+    double h[3];
 };
 
 // Fields of one precision.  Block levels store the interior of each block split by
@@ -83,6 +96,12 @@ struct K {
     static void zero(const Launch &L, T *p, size_t n);
     static void fill(const Launch &L, T *p, size_t n, T value);
     static void scatter(const Launch &L, T *dst, const double *src, int nleafblk);
+    // uniform tail grids run as ordinary launches (large tail levels)
+    static void ugsrb(const Launch &L, const Plane<T> &P, const UGrid &g, int colour, bool var);
+    static void ughost(const Launch &L, const Plane<T> &P, const UGrid &g);
+    static void ufas(const Launch &L, const Plane<T> &P, const UGrid &g, bool var);
+    static void urestrict(const Launch &L, const Plane<T> &P, const UGrid &g, const UGrid &gc, bool var);
+    static void ucorrect(const Launch &L, const Plane<T> &P, const UGrid &g, const UGrid &gc);
     static void gather(const Launch &L, const T *src, double *dst, int nleafblk);
 };
 
@@ -127,6 +146,7 @@ struct HostTree {
     std::vector<int32_t> ncell;                 // [ndom][MAXLEV][3]
     std::vector<int64_t> tail_off;              // [ndom][MAXLEV]
     int64_t tail_cells = 0;                     // padded cells of every tail grid
+    std::vector<int32_t> tail_top;              // [ndom] top level of the one-workgroup tail part
     int64_t nleaf_cells = 0;
     std::vector<int64_t> dom_leaf_cells;
     bool refined = false;                       // any block above a base level

@@ -908,11 +908,12 @@ struct Tail {
 };
 
 // Padded cells of all tail grids of domain dm (levels 0..nt-1 are stored in order).
-__device__ __forceinline__ int64_t tail_span(const DevTables &tb, int dm, int nt, int dim, int64_t *first) {
+// Padded cells of the tail grids 0..top of domain dm (stored in level order).
+__device__ __forceinline__ int64_t tail_span(const DevTables &tb, int dm, int top, int dim, int64_t *first) {
     *first = tb.tail_off[(size_t)dm * MAXLEV];
-    const int32_t *nc = tb.ncell + ((size_t)dm * MAXLEV + nt - 1) * 3;
+    const int32_t *nc = tb.ncell + ((size_t)dm * MAXLEV + top) * 3;
     int64_t last = (int64_t)(nc[0] + 2) * (nc[1] + 2) * (dim == 3 ? nc[2] + 2 : 1);
-    return tb.tail_off[(size_t)dm * MAXLEV + nt - 1] + last - *first;
+    return tb.tail_off[(size_t)dm * MAXLEV + top] + last - *first;
 }
 
 // Caches the tail geometry of domain dm (offsets relative to its first tail array)
@@ -946,8 +947,9 @@ __global__ void __launch_bounds__(512) k_tail(Plane<T> P, DevTables tb, int nt, 
     __shared__ TailBC bcs;
     const int dm = blockIdx.x;
     if (!((mask >> dm) & 1)) return;
+    const int top = tb.tail_top[dm];
     int64_t first;
-    const int64_t n = tail_span(tb, dm, nt, D, &first);
+    const int64_t n = tail_span(tb, dm, top, D, &first);
     tail_setup(tb, dm, nt, D, first, lvs, &bcs);
     const int nf = VAR ? 4 : 3;
     const bool lds = n * nf * (int64_t)sizeof(T) <= lds_bytes;
@@ -964,8 +966,7 @@ __global__ void __launch_bounds__(512) k_tail(Plane<T> P, DevTables tb, int nt, 
         if (VAR) tl.teps = s + 3 * n;
     }
     __syncthreads();
-    const int top = nt - 1;
-    // The restriction from the lowest block level left R(v) in v and R(r) in f.
+    // The restriction from the level above left R(v) in v and R(r) in f.
     tl.finish_fas(top);
     int steps;
     if (mode == TAIL_VCYCLE) {
@@ -997,7 +998,7 @@ __global__ void __launch_bounds__(512) k_tail_eps(Plane<T> P, DevTables tb, int 
     __shared__ TailBC bcs;
     const int dm = blockIdx.x;
     int64_t first;
-    tail_span(tb, dm, nt, D, &first);
+    tail_span(tb, dm, nt - 1, D, &first);
     tail_setup(tb, dm, nt, D, first, lvs, &bcs);
     __syncthreads();
     Tail<T, D, true> tl{lvs, &bcs, red, P.tv + first, P.tvold + first, P.tf + first, P.teps + first};
@@ -1018,6 +1019,165 @@ __global__ void __launch_bounds__(512) k_tail_eps(Plane<T> P, DevTables tb, int 
         tl.ghosts(l, tl.teps, true);
         __syncthreads();
     }
+}
+
+// ------------------------------------------------- large tail grids (uniform)
+// Tail levels with many cells run as ordinary multi-workgroup launches over one
+// domain's uniform grid (one ghost layer).  The operations are those of the block
+// levels: a colour of Gauss-Seidel that pushes the mirroring ghosts (every axis has
+// an even cell count, so a ghost has the colour of the cell it mirrors), the
+// restriction with the residual, the FAS right-hand side and the correction.
+__device__ __forceinline__ int64_t uidx(const UGrid &g, int i, int j, int k, int dim) {
+    if (dim == 2) return g.off + (int64_t)(j + 1) * (g.n[0] + 2) + (i + 1);
+    return g.off + ((int64_t)(k + 1) * (g.n[1] + 2) + (j + 1)) * (g.n[0] + 2) + (i + 1);
+}
+
+template <typename T, int D, bool VAR>
+__device__ __forceinline__ void ustencil(const Plane<T> &P, const UGrid &g, int i, int j, int k, T *w, T *nb) {
+    nb[0] = P.tv[uidx(g, i - 1, j, k, D)];
+    nb[1] = P.tv[uidx(g, i + 1, j, k, D)];
+    nb[2] = P.tv[uidx(g, i, j - 1, k, D)];
+    nb[3] = P.tv[uidx(g, i, j + 1, k, D)];
+    if (D == 3) {
+        nb[4] = P.tv[uidx(g, i, j, k - 1, D)];
+        nb[5] = P.tv[uidx(g, i, j, k + 1, D)];
+    }
+    for (int f = 0; f < 2 * D; f++) w[f] = T(1.0 / (g.h[f >> 1] * g.h[f >> 1]));
+    if (VAR) {
+        const T e0 = P.teps[uidx(g, i, j, k, D)];
+        const int o[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k}, {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+        for (int f = 0; f < 2 * D; f++) w[f] *= harm(e0, P.teps[uidx(g, o[f][0], o[f][1], o[f][2], D)]);
+    }
+}
+
+// Writes the ghosts that mirror cell (i,j,k) of a uniform grid after it changed.
+template <typename T, int D>
+__device__ __forceinline__ void upush(const Plane<T> &P, const DevTables &tb, const UGrid &g, int i, int j, int k,
+                                      T nv) {
+    const int c[3] = {i, j, k};
+    for (int a = 0; a < D; a++) {
+        int side;
+        if (c[a] == 0) side = 0;
+        else if (c[a] == g.n[a] - 1) side = 1;
+        else continue;
+        const int f = 2 * a + side;
+        int q[3] = {i, j, k};
+        const int kind = tb.bck[6 * g.dm + f];
+        T val;
+        if (kind == MG_BC_PERIODIC) {
+            q[a] = side ? -1 : g.n[a];      // the opposite face's ghost
+            val = nv;
+        } else {
+            q[a] = side ? g.n[a] : -1;
+            val = bc_ghost<T>(kind, tb.bcv[6 * g.dm + f], g.h[a], side, nv);
+        }
+        P.tv[uidx(g, q[0], q[1], q[2], D)] = val;
+    }
+}
+
+template <typename T, int D, bool VAR>
+__global__ void __launch_bounds__(256) k_ugsrb(Plane<T> P, DevTables tb, UGrid g, int colour) {
+    const int half = g.n[0] / 2;
+    const int64_t nh = (int64_t)half * g.n[1] * (D == 3 ? g.n[2] : 1);
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nh) return;
+    const int row = (int)(q / half), pos = (int)(q % half);
+    const int j = row % g.n[1], k = D == 3 ? row / g.n[1] : 0;
+    const int i = 2 * pos + ((j + k + colour) & 1);
+    T w[6], nb[6];
+    ustencil<T, D, VAR>(P, g, i, j, k, w, nb);
+    T num = T(0), den = T(0);
+    for (int f = 0; f < 2 * D; f++) {
+        num += w[f] * nb[f];
+        den += w[f];
+    }
+    const int64_t o = uidx(g, i, j, k, D);
+    const T nv = (num - P.tf[o]) / den;
+    P.tv[o] = nv;
+    upush<T, D>(P, tb, g, i, j, k, nv);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_ughost(Plane<T> P, DevTables tb, UGrid g) {
+    const int64_t n = (int64_t)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1);
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int i = (int)(q % g.n[0]);
+    const int r = (int)(q / g.n[0]);
+    const int j = r % g.n[1], k = D == 3 ? r / g.n[1] : 0;
+    const bool edge = i == 0 || i == g.n[0] - 1 || j == 0 || j == g.n[1] - 1 ||
+                      (D == 3 && (k == 0 || k == g.n[2] - 1));
+    if (edge) upush<T, D>(P, tb, g, i, j, k, P.tv[uidx(g, i, j, k, D)]);
+}
+
+template <typename T, int D, bool VAR>
+__global__ void __launch_bounds__(256) k_ufas(Plane<T> P, DevTables tb, UGrid g) {
+    const int64_t npad = (int64_t)(g.n[0] + 2) * (g.n[1] + 2) * (D == 3 ? g.n[2] + 2 : 1);
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npad) return;
+    P.tvold[g.off + q] = P.tv[g.off + q];
+    const int i = (int)(q % (g.n[0] + 2)) - 1;
+    const int r = (int)(q / (g.n[0] + 2));
+    const int j = r % (g.n[1] + 2) - 1, k = D == 3 ? r / (g.n[1] + 2) - 1 : 0;
+    if (i < 0 || i >= g.n[0] || j < 0 || j >= g.n[1] || (D == 3 && (k < 0 || k >= g.n[2]))) return;
+    T w[6], nb[6];
+    ustencil<T, D, VAR>(P, g, i, j, k, w, nb);
+    const T vc = P.tv[g.off + q];
+    T lv = T(0);
+    for (int f = 0; f < 2 * D; f++) lv += w[f] * (nb[f] - vc);
+    P.tf[g.off + q] += lv;
+}
+
+template <typename T, int D, bool VAR>
+__global__ void __launch_bounds__(256) k_urestrict(Plane<T> P, DevTables tb, UGrid g, UGrid gc) {
+    const int64_t n = (int64_t)gc.n[0] * gc.n[1] * (D == 3 ? gc.n[2] : 1);
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int I = (int)(q % gc.n[0]);
+    const int r = (int)(q / gc.n[0]);
+    const int J = r % gc.n[1], K = D == 3 ? r / gc.n[1] : 0;
+    T sv = T(0), sr = T(0);
+    for (int c = 0; c < (1 << D); c++) {
+        const int i = 2 * I + (c & 1), j = 2 * J + ((c >> 1) & 1), k = D == 3 ? 2 * K + (c >> 2) : 0;
+        T w[6], nb[6];
+        ustencil<T, D, VAR>(P, g, i, j, k, w, nb);
+        const int64_t o = uidx(g, i, j, k, D);
+        const T vc = P.tv[o];
+        T lv = T(0);
+        for (int f = 0; f < 2 * D; f++) lv += w[f] * (nb[f] - vc);
+        sv += vc;
+        sr += P.tf[o] - lv;
+    }
+    const T inv = T(1) / T(1 << D);
+    const int64_t oc = uidx(gc, I, J, K, D);
+    P.tv[oc] = sv * inv;
+    P.tf[oc] = sr * inv;
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_ucorrect(Plane<T> P, DevTables tb, UGrid g, UGrid gc) {
+    const int64_t n = (int64_t)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1);
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int i = (int)(q % g.n[0]);
+    const int r = (int)(q / g.n[0]);
+    const int j = r % g.n[1], k = D == 3 ? r / g.n[1] : 0;
+    const int p[3] = {i >> 1, j >> 1, k >> 1};
+    const int sg[3] = {(i & 1) ? 1 : -1, (j & 1) ? 1 : -1, (k & 1) ? 1 : -1};
+    const int64_t o = uidx(gc, p[0], p[1], p[2], D);
+    const T d0 = P.tv[o] - P.tvold[o];
+    T dn[3];
+    for (int a = 0; a < D; a++) {
+        int c[3] = {p[0], p[1], p[2]};
+        c[a] += sg[a];
+        const int64_t oq = uidx(gc, c[0], c[1], c[2], D);
+        dn[a] = P.tv[oq] - P.tvold[oq];
+    }
+    const T corr = D == 2 ? T(0.25) * (T(2) * d0 + dn[0] + dn[1]) : T(0.25) * (d0 + dn[0] + dn[1] + dn[2]);
+    const int64_t of = uidx(g, i, j, k, D);
+    const T nv = P.tv[of] + corr;
+    P.tv[of] = nv;
+    upush<T, D>(P, tb, g, i, j, k, nv);
 }
 
 // ------------------------------------------------------------ small utilities
@@ -1333,6 +1493,60 @@ template <typename T>
 void K<T>::tail_eps(const Launch &L, const Plane<T> &P) {
     if (L.dim == 3) k_tail_eps<T, 3><<<L.ndom, 512, 0, L.stream>>>(P, L.tb, L.nt);
     else k_tail_eps<T, 2><<<L.ndom, 512, 0, L.stream>>>(P, L.tb, L.nt);
+}
+
+static inline unsigned ublocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+static inline int64_t ucells(const UGrid &g, int dim) { return (int64_t)g.n[0] * g.n[1] * (dim == 3 ? g.n[2] : 1); }
+
+template <typename T>
+void K<T>::ugsrb(const Launch &L, const Plane<T> &P, const UGrid &g, int colour, bool var) {
+    const unsigned nb = ublocks(ucells(g, L.dim) / 2);
+    if (L.dim == 3) {
+        if (var) k_ugsrb<T, 3, true><<<nb, 256, 0, L.stream>>>(P, L.tb, g, colour);
+        else k_ugsrb<T, 3, false><<<nb, 256, 0, L.stream>>>(P, L.tb, g, colour);
+    } else {
+        if (var) k_ugsrb<T, 2, true><<<nb, 256, 0, L.stream>>>(P, L.tb, g, colour);
+        else k_ugsrb<T, 2, false><<<nb, 256, 0, L.stream>>>(P, L.tb, g, colour);
+    }
+}
+
+template <typename T>
+void K<T>::ughost(const Launch &L, const Plane<T> &P, const UGrid &g) {
+    const unsigned nb = ublocks(ucells(g, L.dim));
+    if (L.dim == 3) k_ughost<T, 3><<<nb, 256, 0, L.stream>>>(P, L.tb, g);
+    else k_ughost<T, 2><<<nb, 256, 0, L.stream>>>(P, L.tb, g);
+}
+
+template <typename T>
+void K<T>::ufas(const Launch &L, const Plane<T> &P, const UGrid &g, bool var) {
+    const int64_t npad = (int64_t)(g.n[0] + 2) * (g.n[1] + 2) * (L.dim == 3 ? g.n[2] + 2 : 1);
+    const unsigned nb = ublocks(npad);
+    if (L.dim == 3) {
+        if (var) k_ufas<T, 3, true><<<nb, 256, 0, L.stream>>>(P, L.tb, g);
+        else k_ufas<T, 3, false><<<nb, 256, 0, L.stream>>>(P, L.tb, g);
+    } else {
+        if (var) k_ufas<T, 2, true><<<nb, 256, 0, L.stream>>>(P, L.tb, g);
+        else k_ufas<T, 2, false><<<nb, 256, 0, L.stream>>>(P, L.tb, g);
+    }
+}
+
+template <typename T>
+void K<T>::urestrict(const Launch &L, const Plane<T> &P, const UGrid &g, const UGrid &gc, bool var) {
+    const unsigned nb = ublocks(ucells(gc, L.dim));
+    if (L.dim == 3) {
+        if (var) k_urestrict<T, 3, true><<<nb, 256, 0, L.stream>>>(P, L.tb, g, gc);
+        else k_urestrict<T, 3, false><<<nb, 256, 0, L.stream>>>(P, L.tb, g, gc);
+    } else {
+        if (var) k_urestrict<T, 2, true><<<nb, 256, 0, L.stream>>>(P, L.tb, g, gc);
+        else k_urestrict<T, 2, false><<<nb, 256, 0, L.stream>>>(P, L.tb, g, gc);
+    }
+}
+
+template <typename T>
+void K<T>::ucorrect(const Launch &L, const Plane<T> &P, const UGrid &g, const UGrid &gc) {
+    const unsigned nb = ublocks(ucells(g, L.dim));
+    if (L.dim == 3) k_ucorrect<T, 3><<<nb, 256, 0, L.stream>>>(P, L.tb, g, gc);
+    else k_ucorrect<T, 2><<<nb, 256, 0, L.stream>>>(P, L.tb, g, gc);
 }
 
 template <typename T>

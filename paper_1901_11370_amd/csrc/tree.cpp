@@ -298,6 +298,24 @@ std::string build_tree(HostTree &T, const mg_domain *doms, int ndom, int bs, int
         }
     }
     T.tail_cells = off;
+    // Large tail levels (more than kTailBig cells, all axes even so a sweep can push
+    // its ghosts) run as multi-workgroup launches; the rest in one workgroup.
+    T.tail_top.assign(ndom, nt - 1);
+    for (int i = 0; i < ndom; i++) {
+        int l = nt - 1;
+        while (l > 0) {
+            int64_t c = 1;
+            bool even = true;
+            for (int a = 0; a < dim; a++) {
+                int n = T.ncell[((size_t)i * MAXLEV + l) * 3 + a];
+                c *= n;
+                even = even && n % 2 == 0;
+            }
+            if (c <= kTailBig || !even) break;
+            l--;
+        }
+        T.tail_top[i] = l;
+    }
     return "";
 }
 

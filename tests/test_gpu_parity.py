@@ -109,6 +109,33 @@ def test_neumann_and_periodic_mix_3d():
     _run(w, "vvfv")
 
 
+def _smooth_eps(dom, lay, amp=0.6):
+    x = W.cell_centres(lay, dom)
+    return np.exp(amp * np.prod(np.sin(2 * np.pi * x / (np.array(dom.hi) - np.array(dom.lo))), axis=1))
+
+
+def test_large_tail_grids_2d_mixed_bc_variable_eps():
+    # 240 x 144 cells in 16^2 blocks: (15, 9) blocks on the lowest block level, so the
+    # grid below it (120 x 72) runs as multi-workgroup launches
+    dom = W.Domain(2, [240, 144], [0, 0], [1.0, 0.6], [W.NEUMANN, W.DIRICHLET, W.DIRICHLET, W.NEUMANN],
+                   [0.4, 1.0, -0.5, 0.0])
+    g = W.Gaussians(np.array([[0.3, 0.2], [0.7, 0.4]]), np.array([2.0, -1.0]), np.array([0.08, 0.05]))
+    w = W.Workload("bigtail2d", [dom], bs=16, variable_eps=True,
+                   rhs=lambda i, lay: g(W.cell_centres(lay, dom)), eps=lambda i, lay: _smooth_eps(dom, lay))
+    _run(w, "fvvn")
+
+
+def test_large_tail_grids_3d_periodic_neumann():
+    # 96 x 96 x 64 cells in 16^3 blocks: a 24 x 24 x 16 grid below the block levels
+    dom = W.Domain(3, [96, 96, 64], [0, 0, 0], [1.5, 1.5, 1.0], [W.PERIODIC, W.PERIODIC, W.NEUMANN, W.NEUMANN,
+                                                                  W.DIRICHLET, W.DIRICHLET],
+                   [0.0, 0.0, 0.2, -0.1, 1.0, 0.5])
+    g = W.Gaussians(np.array([[0.7, 0.5, 0.4]]), np.array([5.0]), np.array([0.15]))
+    w = W.Workload("bigtail3d", [dom], bs=16, variable_eps=True,
+                   rhs=lambda i, lay: g(W.cell_centres(lay, dom)), eps=lambda i, lay: _smooth_eps(dom, lay, 0.4))
+    _run(w, "vfvv")
+
+
 def test_face_gradient_matches_reference():
     w = W.config5(sizes=(32, 48))
     t = gpu_tree(w)
