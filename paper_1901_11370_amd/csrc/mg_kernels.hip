@@ -210,6 +210,57 @@ __device__ __forceinline__ void push_ghosts(T *__restrict__ vg, const DevTables 
     }
 }
 
+// Per-block data every block kernel needs (domain, neighbours, spacing, boundary
+// conditions), read with scalar loads at kernel start so that they travel together
+// with the first data loads instead of forming a chain of dependent round trips.
+template <int D>
+struct BlockCtx {
+    int dm;
+    int nbr[6];
+    double h[3];
+    int bck[6];
+    double bcv[6];
+    __device__ __forceinline__ void load(const DevTables &tb, int64_t b, int lev) {
+        dm = tb.dom[b];
+#pragma unroll
+        for (int f = 0; f < 2 * D; f++) nbr[f] = tb.nbr[6 * b + f];
+        const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
+#pragma unroll
+        for (int a = 0; a < D; a++) h[a] = hh[a];
+#pragma unroll
+        for (int f = 0; f < 2 * D; f++) {
+            bck[f] = tb.bck[6 * dm + f];
+            bcv[f] = tb.bcv[6 * dm + f];
+        }
+    }
+};
+
+// push_ghosts with the block's data preloaded.
+template <typename T, int D, int BS>
+__device__ __forceinline__ void push_ghosts(T *__restrict__ vg, const BlockCtx<D> &c, int64_t b, int i, int j,
+                                            int k, T nv) {
+    using g = G<D, BS>;
+    const int coord[3] = {i, j, k};
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        int side;
+        if (coord[a] == 0) side = 0;
+        else if (coord[a] == BS - 1) side = 1;
+        else continue;
+        const int f = 2 * a + side;
+        const int a1 = a == 0 ? j : i, a2 = a == 2 ? j : k;
+        // selects, not a run-time array index (which would live in scratch memory)
+        const int n = side ? c.nbr[2 * a + 1] : c.nbr[2 * a];
+        if (n >= 0) {
+            vg[(int64_t)n * g::NG + g::gh(f ^ 1, a1, a2)] = nv;
+        } else if (n == -1) {
+            const int kind = side ? c.bck[2 * a + 1] : c.bck[2 * a];
+            const double val = side ? c.bcv[2 * a + 1] : c.bcv[2 * a];
+            vg[b * g::NG + g::gh(f, a1, a2)] = bc_ghost<T>(kind, val, c.h[a], side, nv);
+        }
+    }
+}
+
 // ------------------------------------------------------------ GS-RB sweep
 // One colour of red-black Gauss-Seidel (Sec. 2.2) for the blocks of one level, one
 // workgroup per block.  The other colour of the block and the other-colour halves of
@@ -230,11 +281,10 @@ __global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev,
     __shared__ __align__(16) T s_eo[VAR ? g::NH : 1];
     __shared__ __align__(16) T s_eg[VAR ? NGH : 1];
     const int64_t b = b0 + blockIdx.x;
-    const int dm = tb.dom[b];
-    if (!((mask >> dm) & 1)) return;
     const int oc = colour ^ 1;
     const int tid = threadIdx.x;
-    // issue every load of this thread first: other colour, its ghosts, own f (and eps)
+    // issue every load of this thread first: other colour, its ghosts, own f (and eps),
+    // the block's tables; a block of a domain outside the mask leaves after staging
     Stager<T, 1, g::NH, 0, TPB> st_o;
     Stager<T, 2 * D, HF, g::NF, TPB> st_g;
     st_o.load(P.v + b * g::NC + oc * g::NH);
@@ -250,6 +300,8 @@ __global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev,
 #pragma unroll
         for (int m = 0; m < IT; m++) er[m] = P.eps[b * g::NC + colour * g::NH + tid + m * TPB];
     }
+    BlockCtx<D> cx;
+    cx.load(tb, b, lev);
     st_o.store(s_o);
     st_g.store(s_g);
     if (VAR) {
@@ -257,10 +309,10 @@ __global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev,
         st_eg.store(s_eg);
     }
     __syncthreads();
-    const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
+    if (!((mask >> cx.dm) & 1)) return;
     T ih2[3];
 #pragma unroll
-    for (int a = 0; a < 3; a++) ih2[a] = T(1.0 / (hh[a] * hh[a]));
+    for (int a = 0; a < 3; a++) ih2[a] = a < D ? T(1.0 / (cx.h[a] * cx.h[a])) : T(0);
 #pragma unroll
     for (int m = 0; m < IT; m++) {
         const int q = tid + m * TPB;
@@ -297,7 +349,7 @@ __global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev,
         }
         const T nv = (num - fval) / den;
         P.v[b * g::NC + colour * g::NH + q] = nv;
-        push_ghosts<T, D, BS>(P.vg, tb, b, dm, hh, i, j, k, nv);
+        push_ghosts<T, D, BS>(P.vg, cx, b, i, j, k, nv);
     }
 }
 
@@ -427,9 +479,14 @@ __global__ void __launch_bounds__(256) k_restrict(Plane<T> P, DevTables tb, int 
     constexpr int IT = (NQ + TPB - 1) / TPB;
     __shared__ __align__(16) T s_v[FAS ? g::NC + g::NG : 4];
     const int64_t b = b0 + blockIdx.x;
-    const int dm = tb.dom[b];
-    if (!((mask >> dm) & 1)) return;
     const int tid = threadIdx.x;
+    // tables first (independent loads): domain, parent, origin; the parent's
+    // neighbours follow once the parent is known
+    const int dm = tb.dom[b];
+    const int64_t p = tb.parent[b];
+    const int ob[3] = {tb.org[3 * b], tb.org[3 * b + 1], tb.org[3 * b + 2]};
+    BlockCtx<D> px;
+    if (MODE != RESTRICT_EPS && p >= 0) px.load(tb, p, lev - 1);
     // fine values of this thread's coarse cells (the field itself, or f for FAS)
     const T *src = MODE == RESTRICT_EPS ? P.eps : (FAS ? P.f : P.v);
     T pre[IT][1 << D];
@@ -450,12 +507,14 @@ __global__ void __launch_bounds__(256) k_restrict(Plane<T> P, DevTables tb, int 
         st_g.store(s_v + g::NC);
         __syncthreads();
     }
+    if (!((mask >> dm) & 1)) return;
     const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
     T ih2[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) ih2[a] = T(1.0 / (hh[a] * hh[a]));
-    const int64_t p = tb.parent[b];
-    const int ob[3] = {tb.org[3 * b], tb.org[3 * b + 1], tb.org[3 * b + 2]};
+    // offset of this block's octant in its parent
+    int po[3] = {0, 0, 0};
+    for (int a = 0; a < D; a++) po[a] = ((ob[a] / BS) & 1) * HB;
 #pragma unroll
     for (int m = 0; m < IT; m++) {
         const int t = tid + m * TPB;
@@ -506,15 +565,14 @@ __global__ void __launch_bounds__(256) k_restrict(Plane<T> P, DevTables tb, int 
         sr *= inv;
         const int gc[3] = {(ob[0] >> 1) + ci, (ob[1] >> 1) + cj, D == 3 ? (ob[2] >> 1) + ck : 0};
         if (p >= 0) {
-            const int l0 = gc[0] - tb.org[3 * p], l1 = gc[1] - tb.org[3 * p + 1], l2 = D == 3 ? gc[2] - tb.org[3 * p + 2] : 0;
+            const int l0 = po[0] + ci, l1 = po[1] + cj, l2 = D == 3 ? po[2] + ck : 0;
             const int64_t o = p * g::NC + g::in(l0, l1, l2);
             if (MODE == RESTRICT_EPS) {
                 P.eps[o] = sv;
             } else {
                 P.v[o] = sv;
                 if (FAS) P.f[o] = sr;
-                const double *hp = tb.h + ((size_t)dm * MAXLEV + lev - 1) * 3;
-                push_ghosts<T, D, BS>(P.vg, tb, p, dm, hp, l0, l1, l2, sv);
+                push_ghosts<T, D, BS>(P.vg, px, p, l0, l1, l2, sv);
             }
         } else {
             const TailGeo tg = tail_geo(tb, dm, nt - 1, D);
@@ -535,19 +593,23 @@ __global__ void __launch_bounds__(256) k_fas(Plane<T> P, DevTables tb, int lev, 
                                              uint64_t mask, int wg_per_block) {
     using g = G<D, BS>;
     const int64_t b = list[blockIdx.x / wg_per_block];
-    const int dm = tb.dom[b];
-    if (!((mask >> dm) & 1)) return;
     const int t = (blockIdx.x % wg_per_block) * blockDim.x + threadIdx.x;
+    // the domain test comes last so that the data loads need not wait for it
+    const int dm = tb.dom[b];
     if (t < g::NC) {
         const Spacing s = spacing(tb, dm, lev);
         int i, j, k;
         g::decode(t, i, j, k);
         Stencil<T, D, BS, VAR> st;
         st.load(P, b, i, j, k, s, true);
+        const T fv = P.f[b * g::NC + t];
+        if (!((mask >> dm) & 1)) return;
         P.vold[b * g::NC + t] = st.vc;
-        P.f[b * g::NC + t] += st.Lv();
+        P.f[b * g::NC + t] = fv + st.Lv();
     } else if (t < g::NC + g::NG) {
-        P.voldg[b * g::NG + t - g::NC] = P.vg[b * g::NG + t - g::NC];
+        const T gv = P.vg[b * g::NG + t - g::NC];
+        if (!((mask >> dm) & 1)) return;
+        P.voldg[b * g::NG + t - g::NC] = gv;
     }
 }
 
@@ -567,14 +629,16 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
     constexpr int TPB = g::NC < 256 ? g::NC : 256;
     __shared__ T s_d[NBOX];
     const int64_t b = b0 + blockIdx.x;
-    const int dm = tb.dom[b];
-    if (!((mask >> dm) & 1)) return;
     const int tid = threadIdx.x;
+    // the block's tables, all independent loads; the octant of the block in its parent
+    // follows from its own origin (block coordinates' parity)
+    BlockCtx<D> cx;
+    cx.load(tb, b, lev);
+    const int dm = cx.dm;
     const int64_t p = tb.parent[b];
     const int gc0[3] = {tb.org[3 * b] >> 1, tb.org[3 * b + 1] >> 1, D == 3 ? tb.org[3 * b + 2] >> 1 : 0};
     int po[3] = {0, 0, 0};
-    if (p >= 0)
-        for (int a = 0; a < D; a++) po[a] = gc0[a] - tb.org[3 * p + a];
+    for (int a = 0; a < D; a++) po[a] = ((gc0[a] / HB) & 1) * HB;
     constexpr int ITB = (NBOX + TPB - 1) / TPB;
     constexpr int IT = (g::NC + TPB - 1) / TPB;
     const TailGeo tg = tail_geo(tb, dm, nt - 1, D);
@@ -618,7 +682,7 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
         if (q < NBOX) s_d[q] = dv[m];
     }
     __syncthreads();
-    const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
+    if (!((mask >> dm) & 1)) return;
 #pragma unroll
     for (int m = 0; m < IT; m++) {
         const int t = tid + m * TPB;
@@ -634,7 +698,7 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
         else corr = T(0.25) * (d0 + dx + dy + s_d[c0 + sz * HP * HP]);
         const T nv = vr[m] + corr;
         P.v[b * g::NC + t] = nv;
-        push_ghosts<T, D, BS>(P.vg, tb, b, dm, hh, i, j, k, nv);
+        push_ghosts<T, D, BS>(P.vg, cx, b, i, j, k, nv);
     }
 }
 
@@ -1254,13 +1318,16 @@ __global__ void __launch_bounds__(256) k_norm(Plane<double> P, DevTables tb, dou
         const int t = tid + m * TPB;
         fr[m] = P.f[b * g::NC + (g::NC % TPB == 0 || t < g::NC ? t : 0)];
     }
+    const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
+    const double h0 = hh[0], h1 = hh[1], h2 = hh[2];
     st_v.store(s_v);
     st_g.store(s_v + g::NC);
     __syncthreads();
-    const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
     double ih2[3];
-    for (int a = 0; a < 3; a++) ih2[a] = 1.0 / (hh[a] * hh[a]);
-    const double vol = hh[0] * hh[1] * (D == 3 ? hh[2] : 1.0);
+    ih2[0] = 1.0 / (h0 * h0);
+    ih2[1] = 1.0 / (h1 * h1);
+    ih2[2] = 1.0 / (h2 * h2);
+    const double vol = h0 * h1 * (D == 3 ? h2 : 1.0);
     double mr = 0, sr = 0, mf = 0, sf = 0;
 #pragma unroll
     for (int m = 0; m < IT; m++) {
