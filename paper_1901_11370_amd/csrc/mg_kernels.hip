@@ -703,123 +703,194 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
 }
 
 // --------------------------------------------------------------- the tail
-// One workgroup per domain runs everything below the lowest block level: the levels
-// whose block size was halved down to one cell (Sec. 2.5; the paper keeps them on a
-// single process).  They are uniform grids, so each is stored whole with one ghost
-// layer; blocked red-black Gauss-Seidel with ghost refresh after each colour equals a
-// sweep over the whole grid.
-// Geometry of one tail grid and the domain's boundary data, cached in LDS.
+// One workgroup per domain runs the coarse grids below the lowest block level: the
+// levels whose block size was halved down to one cell (Sec. 2.5; the paper keeps
+// them on a single process), except the large ones that the grid-wide launches
+// handle.  They are uniform grids, stored whole with one ghost layer.  Red-black
+// Gauss-Seidel over the whole grid: a cell that changes writes the ghosts that mirror
+// it (a ghost then holds the other colour's value, so a sweep never reads what it
+// writes), except on grids with an odd cell count along a periodic axis, where the
+// two ends of a row share a colour and the ghost layer is refilled after each colour.
+// When a domain's grids fit in LDS they are copied in, cycled there and copied back.
+
+// Operations of a tail cycle.
+enum { TOP_ENTER = 0, TOP_DOWN, TOP_UP, TOP_RESTRICT, TOP_CORRECT, TOP_COARSE };
+constexpr int kTailOps = 512;
+
+// Geometry of one tail grid (offsets relative to the domain's first tail array).
 struct TailLev {
-    TailGeo g;            // cells per axis and offset relative to the domain's first tail array
+    int n[3];          // cells per axis (1 on unused axes)
+    int sy, sz;        // padded strides of j and k
+    int off;           // offset of the padded grid
+    int ncell, npad;   // cells, padded cells
+    int rh;            // colour slots per row, (n[0] + 1) / 2
+    int ghost_pass;    // periodic axis with an odd cell count
+    float inv_rh, inv_n0, inv_n1;
     double h[3], ih2[3];
+    double inv_den;    // 1 / (2 sum ih2): the constant-coefficient diagonal
 };
 struct TailBC {
     int kind[6];
     double value[6];
 };
 
+// q = x / d, r = x % d for 0 <= x < 2^22 (a float reciprocal, then one correction).
+__device__ __forceinline__ void divmod(int x, int d, float inv, int &q, int &r) {
+    q = (int)((float)x * inv);
+    r = x - q * d;
+    if (r < 0) {
+        q--;
+        r += d;
+    } else if (r >= d) {
+        q++;
+        r -= d;
+    }
+}
+
+template <int D>
+__device__ __forceinline__ int tix(const TailLev &g, int i, int j, int k) {
+    return g.off + (D == 3 ? (k + 1) * g.sz : 0) + (j + 1) * g.sy + (i + 1);
+}
+
 template <typename T, int D, bool VAR>
 struct Tail {
-    const TailLev *lv;         // [nt] in LDS
+    const TailLev *lv;         // [levels] in LDS
     const TailBC *bc;          // in LDS
-    double *red;               // shared reduction scratch, one slot per wave
-    T *tv, *tvold, *tf, *teps; // this domain's tail arrays (global memory or LDS)
+    double *red;               // reduction scratch in LDS, one slot per wave
+    T *tv, *tvold, *tf, *teps; // this domain's tail arrays (LDS or global memory)
+    T *tvold_top;              // with the arrays in LDS: v_old of the top grid, in global
+    int top;                   // memory (only the block level above reads it)
 
-    __device__ __forceinline__ const TailGeo &geo(int lev) const { return lv[lev].g; }
-    __device__ __forceinline__ int count(const TailGeo &g) const { return g.n[0] * g.n[1] * g.n[2]; }
-    __device__ __forceinline__ void cell(const TailGeo &g, int c, int &i, int &j, int &k) const {
-        i = c % g.n[0];
-        const int r = c / g.n[0];
-        j = r % g.n[1];
-        k = r / g.n[1];
+    __device__ __forceinline__ void cell(const TailLev &g, int c, int &i, int &j, int &k) const {
+        int r;
+        divmod(c, g.n[0], g.inv_n0, r, i);
+        if (D == 3) divmod(r, g.n[1], g.inv_n1, k, j);
+        else { j = r; k = 0; }
     }
+    // Colour slot s of grid g -> cell of that colour; false past the end of a row.
+    __device__ __forceinline__ bool slot(const TailLev &g, int s, int colour, int &i, int &j, int &k) const {
+        int row, pos;
+        divmod(s, g.rh, g.inv_rh, row, pos);
+        if (D == 3) divmod(row, g.n[1], g.inv_n1, k, j);
+        else { j = row; k = 0; }
+        i = 2 * pos + ((j + k + colour) & 1);
+        return i < g.n[0];
+    }
+    __device__ __forceinline__ int nslot(const TailLev &g) const { return g.rh * g.n[1] * (D == 3 ? g.n[2] : 1); }
 
-    // Ghost layer of one tail grid (faces only): periodic copy or boundary condition.
-    __device__ void ghosts(int lev, T *u, bool eps) const {
-        const TailGeo &g = geo(lev);
+    // Writes the ghosts mirroring cell (i,j,k) after it changed to nv (physical faces
+    // always, periodic faces if `periodic`).
+    __device__ __forceinline__ void push(T *u, const TailLev &g, int i, int j, int k, T nv, bool periodic) const {
+        const int c[3] = {i, j, k};
+#pragma unroll
+        for (int a = 0; a < D; a++) {
+#pragma unroll
+            for (int side = 0; side < 2; side++) {
+                if (c[a] != (side ? g.n[a] - 1 : 0)) continue;
+                const int f = 2 * a + side;
+                const int kind = bc->kind[f];
+                int q[3] = {i, j, k};
+                T val;
+                if (kind == MG_BC_PERIODIC) {
+                    if (!periodic) continue;
+                    q[a] = side ? -1 : g.n[a];
+                    val = nv;
+                } else {
+                    q[a] = side ? g.n[a] : -1;
+                    val = bc_ghost<T>(kind, bc->value[f], g.h[a], side, nv);
+                }
+                u[tix<D>(g, q[0], q[1], q[2])] = val;
+            }
+        }
+    }
+    // The whole ghost layer of one grid (faces only): periodic copy or boundary
+    // condition (for eps, a copy of the interior cell).
+    __device__ __forceinline__ void fill_ghosts(int lev, T *u, bool eps) const {
+        const TailLev &g = lv[lev];
+#pragma unroll
         for (int a = 0; a < D; a++) {
             const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
             const int n1 = g.n[t1], n2 = D == 3 ? g.n[t2] : 1;
             const int tot = 2 * n1 * n2;
             for (int q = threadIdx.x; q < tot; q += blockDim.x) {
-                const int side = q / (n1 * n2);
-                const int r = q % (n1 * n2);
+                const int side = q >= n1 * n2;
+                const int r = q - side * n1 * n2;
                 int c[3], in[3], op[3];
-                c[t1] = r % n1; c[t2] = D == 3 ? r / n1 : 0;
-                in[t1] = c[t1]; in[t2] = c[t2]; op[t1] = c[t1]; op[t2] = c[t2];
+                c[t1] = r % n1;
+                c[t2] = D == 3 ? r / n1 : 0;
+                in[t1] = op[t1] = c[t1];
+                in[t2] = op[t2] = c[t2];
                 c[a] = side ? g.n[a] : -1;
                 in[a] = side ? g.n[a] - 1 : 0;
                 op[a] = side ? 0 : g.n[a] - 1;
-                if (D == 2) { c[2] = 0; in[2] = 0; op[2] = 0; }
+                if (D == 2) c[2] = in[2] = op[2] = 0;
                 const int f = 2 * a + side;
                 const int kind = bc->kind[f];
                 T val;
-                if (kind == MG_BC_PERIODIC) val = u[g.idx(op[0], op[1], op[2], D)];
-                else if (eps) val = u[g.idx(in[0], in[1], in[2], D)];
-                else val = bc_ghost<T>(kind, bc->value[f], lv[lev].h[a], side, u[g.idx(in[0], in[1], in[2], D)]);
-                u[g.idx(c[0], c[1], c[2], D)] = val;
+                if (kind == MG_BC_PERIODIC) val = u[tix<D>(g, op[0], op[1], op[2])];
+                else if (eps) val = u[tix<D>(g, in[0], in[1], in[2])];
+                else val = bc_ghost<T>(kind, bc->value[f], g.h[a], side, u[tix<D>(g, in[0], in[1], in[2])]);
+                u[tix<D>(g, c[0], c[1], c[2])] = val;
             }
         }
     }
 
-    __device__ __forceinline__ void weights(int lev, const TailGeo &g, int i, int j, int k, T *w) const {
-        if (!VAR) {
-            for (int f = 0; f < 2 * D; f++) w[f] = T(lv[lev].ih2[f / 2]);
-        } else {
-            const T e0 = teps[g.idx(i, j, k, D)];
-            const int o[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k}, {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
-            for (int f = 0; f < 2 * D; f++)
-                w[f] = harm(e0, teps[g.idx(o[f][0], o[f][1], o[f][2], D)]) * T(lv[lev].ih2[f / 2]);
+    __device__ __forceinline__ void stencil(const TailLev &g, int i, int j, int k, T *w, T *nb) const {
+        const int o = tix<D>(g, i, j, k);
+        const int st[3] = {1, g.sy, g.sz};
+#pragma unroll
+        for (int f = 0; f < 2 * D; f++) {
+            const int d = (f & 1) ? st[f >> 1] : -st[f >> 1];
+            nb[f] = tv[o + d];
+            w[f] = T(g.ih2[f >> 1]);
+            if (VAR) w[f] *= harm(teps[o], teps[o + d]);
         }
     }
-    __device__ __forceinline__ void nbrs(const TailGeo &g, const T *u, int i, int j, int k, T *nb) const {
-        nb[0] = u[g.idx(i - 1, j, k, D)];
-        nb[1] = u[g.idx(i + 1, j, k, D)];
-        nb[2] = u[g.idx(i, j - 1, k, D)];
-        nb[3] = u[g.idx(i, j + 1, k, D)];
-        if (D == 3) {
-            nb[4] = u[g.idx(i, j, k - 1, D)];
-            nb[5] = u[g.idx(i, j, k + 1, D)];
-        }
-    }
-    __device__ __forceinline__ T Lv(int lev, const TailGeo &g, int i, int j, int k) const {
+    __device__ __forceinline__ T Lv(const TailLev &g, int i, int j, int k) const {
         T w[6], nb[6];
-        weights(lev, g, i, j, k, w);
-        nbrs(g, tv, i, j, k, nb);
-        const T vc = tv[g.idx(i, j, k, D)];
+        stencil(g, i, j, k, w, nb);
+        const T vc = tv[tix<D>(g, i, j, k)];
         T s = T(0);
+#pragma unroll
         for (int f = 0; f < 2 * D; f++) s += w[f] * (nb[f] - vc);
         return s;
     }
 
-    __device__ void smooth(int lev) const {
-        const TailGeo &g = geo(lev);
-        const int n = count(g);
-        for (int colour = 0; colour < 2; colour++) {
-            for (int c = threadIdx.x; c < n; c += blockDim.x) {
-                int i, j, k;
-                cell(g, c, i, j, k);
-                if (((i + j + k) & 1) != colour) continue;
-                T w[6], nb[6];
-                weights(lev, g, i, j, k, w);
-                nbrs(g, tv, i, j, k, nb);
-                T num = T(0), den = T(0);
-                for (int f = 0; f < 2 * D; f++) {
-                    num += w[f] * nb[f];
-                    den += w[f];
-                }
-                const int64_t o = g.idx(i, j, k, D);
-                tv[o] = (num - tf[o]) / den;
+    // One colour of Gauss-Seidel on grid lev, then a barrier.
+    __device__ __forceinline__ void sweep(int lev, int colour) const {
+        const TailLev &g = lv[lev];
+        const bool gp = g.ghost_pass;
+        const int ns = nslot(g);
+        for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+            int i, j, k;
+            if (!slot(g, s, colour, i, j, k)) continue;
+            T w[6], nb[6];
+            stencil(g, i, j, k, w, nb);
+            T num = T(0), den = T(0);
+#pragma unroll
+            for (int f = 0; f < 2 * D; f++) {
+                num += w[f] * nb[f];
+                den += w[f];
             }
-            __syncthreads();
-            ghosts(lev, tv, false);
+            const int o = tix<D>(g, i, j, k);
+            const T nv = VAR ? (num - tf[o]) / den : (num - tf[o]) * T(g.inv_den);
+            tv[o] = nv;
+            if (!gp) push(tv, g, i, j, k, nv, true);
+        }
+        __syncthreads();
+        if (gp) {
+            fill_ghosts(lev, tv, false);
             __syncthreads();
         }
+    }
+    __device__ __forceinline__ void smooth(int lev) const {
+        sweep(lev, 0);
+        sweep(lev, 1);
     }
 
     // Block-wide reductions (all threads get the result): wave shuffles, then one
     // exchange through LDS.
-    __device__ double reduce_max(double x) const {
+    __device__ __forceinline__ double reduce_max(double x) const {
         for (int o = 32; o > 0; o >>= 1) {
             double y = __shfl_xor(x, o);
             if (y > x || y != y) x = y;
@@ -832,7 +903,7 @@ struct Tail {
         __syncthreads();
         return x;
     }
-    __device__ double reduce_sum(double x) const {
+    __device__ __forceinline__ double reduce_sum(double x) const {
         for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
         __syncthreads();
@@ -842,79 +913,84 @@ struct Tail {
         return x;
     }
 
-    __device__ double resmax(int lev) const {
-        const TailGeo &g = geo(lev);
-        const int n = count(g);
+    __device__ __forceinline__ double resmax(int lev) const {
+        const TailLev &g = lv[lev];
         double m = 0.0;
-        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
             int i, j, k;
             cell(g, c, i, j, k);
-            const double r = fabs((double)(tf[g.idx(i, j, k, D)] - Lv(lev, g, i, j, k)));
+            const double r = fabs((double)(tf[tix<D>(g, i, j, k)] - Lv(g, i, j, k)));
             if (r > m || r != r) m = r;
         }
         return reduce_max(m);
     }
 
-    // Restriction lev -> lev-1 with the FAS right-hand side (as for block levels).
-    __device__ void restrict_fas(int lev) const {
-        const TailGeo &gf = geo(lev), &gc = geo(lev - 1);
-        const int n = count(gc);
-        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    // v_old = v (ghosts included) and f += L v on grid lev (ghosts already valid).
+    __device__ __forceinline__ void fas(int lev) const {
+        const TailLev &g = lv[lev];
+        if (tvold_top && lev == top) {
+            for (int q = threadIdx.x; q < g.npad; q += blockDim.x) tvold_top[g.off + q] = tv[g.off + q];
+        } else {
+            for (int q = threadIdx.x; q < g.npad; q += blockDim.x) tvold[g.off + q] = tv[g.off + q];
+        }
+        for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
+            int i, j, k;
+            cell(g, c, i, j, k);
+            tf[tix<D>(g, i, j, k)] += Lv(g, i, j, k);
+        }
+        __syncthreads();
+    }
+    // Entry to the top grid, which a restriction from above filled without ghosts.
+    __device__ __forceinline__ void enter(int lev) const {
+        fill_ghosts(lev, tv, false);
+        __syncthreads();
+        fas(lev);
+    }
+    // Restriction lev -> lev-1 of v and of the residual (pushing the coarse ghosts),
+    // then the FAS right-hand side there.
+    __device__ __forceinline__ void restrict_fas(int lev) const {
+        const TailLev &gf = lv[lev], &gc = lv[lev - 1];
+        for (int c = threadIdx.x; c < gc.ncell; c += blockDim.x) {
             int I, J, K;
             cell(gc, c, I, J, K);
             T sv = T(0), sr = T(0);
+#pragma unroll
             for (int q = 0; q < (1 << D); q++) {
                 const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = D == 3 ? 2 * K + (q >> 2) : 0;
-                const int64_t o = gf.idx(i, j, k, D);
+                const int o = tix<D>(gf, i, j, k);
                 sv += tv[o];
-                sr += tf[o] - Lv(lev, gf, i, j, k);
+                sr += tf[o] - Lv(gf, i, j, k);
             }
             const T inv = T(1) / T(1 << D);
-            const int64_t oc = gc.idx(I, J, K, D);
+            const int oc = tix<D>(gc, I, J, K);
             tv[oc] = sv * inv;
             tf[oc] = sr * inv;
+            push(tv, gc, I, J, K, sv * inv, true);
         }
         __syncthreads();
-        finish_fas(lev - 1);
+        fas(lev - 1);
     }
-    // Ghosts, v_old = v (ghosts included), f = R(r) + L v on one tail grid.
-    __device__ void finish_fas(int lev) const {
-        ghosts(lev, tv, false);
-        __syncthreads();
-        const TailGeo &g = geo(lev);
-        const int np = (g.n[0] + 2) * (g.n[1] + 2) * (D == 3 ? g.n[2] + 2 : 1);
-        for (int c = threadIdx.x; c < np; c += blockDim.x) tvold[g.off + c] = tv[g.off + c];
-        const int n = count(g);
-        for (int c = threadIdx.x; c < n; c += blockDim.x) {
-            int i, j, k;
-            cell(g, c, i, j, k);
-            tf[g.idx(i, j, k, D)] += Lv(lev, g, i, j, k);
-        }
-        __syncthreads();
-    }
-
-    __device__ void correct(int lev) const {
-        const TailGeo &gf = geo(lev), &gc = geo(lev - 1);
-        const int n = count(gf);
-        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    // Prolongation of v - v_old from lev-1 (eq. interp_2d / interp_3d) added to lev,
+    // with the ghosts of lev pushed.
+    __device__ __forceinline__ void correct(int lev) const {
+        const TailLev &gf = lv[lev], &gc = lv[lev - 1];
+        for (int c = threadIdx.x; c < gf.ncell; c += blockDim.x) {
             int i, j, k;
             cell(gf, c, i, j, k);
             const int p[3] = {i >> 1, j >> 1, k >> 1};
             const int sg[3] = {(i & 1) ? 1 : -1, (j & 1) ? 1 : -1, (k & 1) ? 1 : -1};
-            const int64_t o = gc.idx(p[0], p[1], p[2], D);
+            const int o = tix<D>(gc, p[0], p[1], p[2]);
             const T d0 = tv[o] - tvold[o];
+            const int st[3] = {1, gc.sy, gc.sz};
             T dn[3];
-            for (int a = 0; a < D; a++) {
-                int q[3] = {p[0], p[1], p[2]};
-                q[a] += sg[a];
-                const int64_t oq = gc.idx(q[0], q[1], q[2], D);
-                dn[a] = tv[oq] - tvold[oq];
-            }
+#pragma unroll
+            for (int a = 0; a < D; a++) dn[a] = tv[o + sg[a] * st[a]] - tvold[o + sg[a] * st[a]];
             const T corr = D == 2 ? T(0.25) * (T(2) * d0 + dn[0] + dn[1]) : T(0.25) * (d0 + dn[0] + dn[1] + dn[2]);
-            tv[gf.idx(i, j, k, D)] += corr;
+            const int of = tix<D>(gf, i, j, k);
+            const T nv = tv[of] + corr;
+            tv[of] = nv;
+            push(tv, gf, i, j, k, nv, true);
         }
-        __syncthreads();
-        ghosts(lev, tv, false);
         __syncthreads();
     }
 
@@ -923,23 +999,22 @@ struct Tail {
     // second on) lowers it by less than 0.1% (rounding floor; the two-value
     // alternation of a one-cell Dirichlet grid).  Fully periodic: remove the mean of
     // f first.
-    __device__ int coarse_solve(const TailParams &tp) const {
-        const TailGeo &g = geo(0);
-        const int n = count(g);
+    __device__ __forceinline__ int coarse_solve(const TailParams &tp) const {
+        const TailLev &g = lv[0];
         bool per = true;
         for (int f = 0; f < 2 * D; f++) per = per && bc->kind[f] == MG_BC_PERIODIC;
         if (per) {
             double s = 0.0;
-            for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
                 int i, j, k;
                 cell(g, c, i, j, k);
-                s += (double)tf[g.idx(i, j, k, D)];
+                s += (double)tf[tix<D>(g, i, j, k)];
             }
-            const double mean = reduce_sum(s) / (double)n;
-            for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            const double mean = reduce_sum(s) / (double)g.ncell;
+            for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
                 int i, j, k;
                 cell(g, c, i, j, k);
-                tf[g.idx(i, j, k, D)] -= T(mean);
+                tf[tix<D>(g, i, j, k)] -= T(mean);
             }
             __syncthreads();
         }
@@ -957,21 +1032,58 @@ struct Tail {
         return k > tp.n_max ? tp.n_max : k;
     }
 
-    __device__ int vcycle(int top, const TailParams &tp) const {
-        for (int l = top; l >= 1; l--) {
-            for (int s = 0; s < tp.n_down; s++) smooth(l);
-            restrict_fas(l);
-        }
-        const int steps = coarse_solve(tp);
-        for (int l = 1; l <= top; l++) {
-            correct(l);
-            for (int s = 0; s < tp.n_up; s++) smooth(l);
+    // Runs a cycle given as a list of operations (each operation's code appears once
+    // in the kernel, which keeps the instruction footprint small).
+    __device__ __forceinline__ int run(const int *ops, int nops, const TailParams &tp) const {
+        int steps = 0;
+        for (int q = 0; q < nops; q++) {
+            const int kind = ops[q] >> 8, l = ops[q] & 255;
+            switch (kind) {
+            case TOP_ENTER: enter(l); break;
+            case TOP_DOWN:
+            case TOP_UP: {
+                const int reps = kind == TOP_DOWN ? tp.n_down : tp.n_up;
+                for (int s = 0; s < reps; s++) smooth(l);
+                break;
+            }
+            case TOP_RESTRICT: restrict_fas(l); break;
+            case TOP_CORRECT: correct(l); break;
+            default: steps = coarse_solve(tp); break;
+            }
         }
         return steps;
     }
 };
 
-// Padded cells of all tail grids of domain dm (levels 0..nt-1 are stored in order).
+// Operation list of a tail V-cycle (mode TAIL_VCYCLE) or FMG cycle (TAIL_FMG) from
+// grid top; at most 2 top^2 + 5 top + 2 entries.
+__device__ __forceinline__ int tail_ops(int *ops, int mode, int top) {
+    int n = 0;
+    ops[n++] = TOP_ENTER << 8 | top;
+    auto vcycle = [&](int t) {
+        for (int l = t; l >= 1; l--) {
+            ops[n++] = TOP_DOWN << 8 | l;
+            ops[n++] = TOP_RESTRICT << 8 | l;
+        }
+        ops[n++] = TOP_COARSE << 8;
+        for (int l = 1; l <= t; l++) {
+            ops[n++] = TOP_CORRECT << 8 | l;
+            ops[n++] = TOP_UP << 8 | l;
+        }
+    };
+    if (mode == TAIL_VCYCLE) {
+        vcycle(top);
+    } else {
+        for (int l = top; l >= 1; l--) ops[n++] = TOP_RESTRICT << 8 | l;
+        ops[n++] = TOP_COARSE << 8;
+        for (int t = 1; t <= top; t++) {
+            ops[n++] = TOP_CORRECT << 8 | t;
+            vcycle(t);
+        }
+    }
+    return n;
+}
+
 // Padded cells of the tail grids 0..top of domain dm (stored in level order).
 __device__ __forceinline__ int64_t tail_span(const DevTables &tb, int dm, int top, int dim, int64_t *first) {
     *first = tb.tail_off[(size_t)dm * MAXLEV];
@@ -980,19 +1092,44 @@ __device__ __forceinline__ int64_t tail_span(const DevTables &tb, int dm, int to
     return tb.tail_off[(size_t)dm * MAXLEV + top] + last - *first;
 }
 
-// Caches the tail geometry of domain dm (offsets relative to its first tail array)
-// and its boundary data in LDS.
-__device__ void tail_setup(const DevTables &tb, int dm, int nt, int dim, int64_t first, TailLev *lv, TailBC *bc) {
-    if (threadIdx.x < nt) {
+// Offset of the padded tail grid `top` of domain dm.
+__device__ __forceinline__ int64_t tail_last_off(const DevTables &tb, int dm, int top) {
+    return tb.tail_off[(size_t)dm * MAXLEV + top];
+}
+
+// Caches the geometry of tail grids 0..nlev-1 of domain dm and its boundary data in
+// LDS.
+__device__ __forceinline__ void tail_setup(const DevTables &tb, int dm, int nlev, int dim, int64_t first, TailLev *lv,
+                           TailBC *bc) {
+    if (threadIdx.x < nlev) {
         const int l = threadIdx.x;
-        TailGeo g = tail_geo(tb, dm, l, dim);
-        g.off -= first;
-        lv[l].g = g;
+        const int32_t *nc = tb.ncell + ((size_t)dm * MAXLEV + l) * 3;
         const double *h = tb.h + ((size_t)dm * MAXLEV + l) * 3;
-        for (int a = 0; a < 3; a++) {
-            lv[l].h[a] = h[a];
-            lv[l].ih2[a] = 1.0 / (h[a] * h[a]);
+        TailLev g;
+        g.n[0] = nc[0];
+        g.n[1] = nc[1];
+        g.n[2] = dim == 3 ? nc[2] : 1;
+        g.sy = g.n[0] + 2;
+        g.sz = (g.n[0] + 2) * (g.n[1] + 2);
+        g.off = (int)(tb.tail_off[(size_t)dm * MAXLEV + l] - first);
+        g.ncell = g.n[0] * g.n[1] * g.n[2];
+        g.npad = g.sz * (dim == 3 ? g.n[2] + 2 : 1);
+        g.rh = (g.n[0] + 1) / 2;
+        g.inv_rh = 1.0f / (float)g.rh;
+        g.inv_n0 = 1.0f / (float)g.n[0];
+        g.inv_n1 = 1.0f / (float)g.n[1];
+        g.ghost_pass = 0;
+        for (int a = 0; a < dim; a++) {
+            if (tb.bck[6 * dm + 2 * a] == MG_BC_PERIODIC && (g.n[a] & 1)) g.ghost_pass = 1;
+            g.h[a] = h[a];
+            g.ih2[a] = 1.0 / (h[a] * h[a]);
         }
+        for (int a = dim; a < 3; a++) {
+            g.h[a] = 1.0;
+            g.ih2[a] = 0.0;
+        }
+        g.inv_den = 1.0 / (2.0 * (g.ih2[0] + g.ih2[1] + g.ih2[2]));
+        lv[l] = g;
     }
     if (threadIdx.x < 6) {
         bc->kind[threadIdx.x] = tb.bck[6 * dm + threadIdx.x];
@@ -1000,56 +1137,52 @@ __device__ void tail_setup(const DevTables &tb, int dm, int nt, int dim, int64_t
     }
 }
 
-// One workgroup per domain.  When the domain's tail grids fit in the dynamic LDS
-// allocation they are copied in, cycled there, and copied back.
+// One workgroup per domain in the mask: the grids 0..tail_top of the domain run a
+// V-cycle or an FMG cycle.
 template <typename T, int D, bool VAR>
-__global__ void __launch_bounds__(512) k_tail(Plane<T> P, DevTables tb, int nt, int mode, uint64_t mask,
-                                              TailParams tp, int32_t *steps_out, int lds_bytes) {
+__global__ void __launch_bounds__(VAR ? 512 : 1024) k_tail(Plane<T> P, DevTables tb, int mode, uint64_t mask,
+                                                           TailParams tp, int32_t *steps_out, int lds_bytes) {
     extern __shared__ double smem[];
     __shared__ double red[16];
     __shared__ TailLev lvs[MAXLEV];
     __shared__ TailBC bcs;
+    __shared__ int ops[kTailOps];
+    __shared__ int nops;
     const int dm = blockIdx.x;
     if (!((mask >> dm) & 1)) return;
     const int top = tb.tail_top[dm];
     int64_t first;
-    const int64_t n = tail_span(tb, dm, top, D, &first);
-    tail_setup(tb, dm, nt, D, first, lvs, &bcs);
-    const int nf = VAR ? 4 : 3;
-    const bool lds = n * nf * (int64_t)sizeof(T) <= lds_bytes;
-    Tail<T, D, VAR> tl{lvs, &bcs, red, P.tv + first, P.tvold + first, P.tf + first, VAR ? P.teps + first : nullptr};
-    if (lds) {
-        T *s = reinterpret_cast<T *>(smem);
-        for (int q = threadIdx.x; q < (int)n; q += blockDim.x) {
-            s[q] = tl.tv[q];
-            s[n + q] = tl.tvold[q];
-            s[2 * n + q] = tl.tf[q];
-            if (VAR) s[3 * n + q] = tl.teps[q];
-        }
-        tl.tv = s; tl.tvold = s + n; tl.tf = s + 2 * n;
-        if (VAR) tl.teps = s + 3 * n;
-    }
-    __syncthreads();
-    // The restriction from the level above left R(v) in v and R(r) in f.
-    tl.finish_fas(top);
+    const int n = (int)tail_span(tb, dm, top, D, &first);
+    tail_setup(tb, dm, top + 1, D, first, lvs, &bcs);
+    if (threadIdx.x == 0) nops = tail_ops(ops, mode, top);
+    // LDS holds v and f of every grid, v_old below the top grid (v_old of the top grid
+    // is written to global memory, where the block level above reads it) and eps.  The
+    // cycle reads only v and f of the top grid (and eps) from outside and leaves only v
+    // and v_old of the top grid to the outside, so only those are copied.
+    const int nold = (int)(tail_last_off(tb, dm, top) - first);    // v_old cells below the top grid
+    const int64_t lds_need = (2 * (int64_t)n + nold + (VAR ? n : 0)) * (int64_t)sizeof(T);
     int steps;
-    if (mode == TAIL_VCYCLE) {
-        steps = tl.vcycle(top, tp);
-    } else {
-        for (int l = top; l >= 1; l--) tl.restrict_fas(l);
-        steps = tl.coarse_solve(tp);
-        for (int l = 1; l <= top; l++) {
-            tl.correct(l);
-            steps = tl.vcycle(l, tp);
-        }
-    }
-    if (lds) {
+    if (lds_need <= lds_bytes) {
+        T *sv = reinterpret_cast<T *>(smem);
+        T *sf = sv + n, *so = sf + n, *se = so + nold;
         __syncthreads();
-        for (int q = threadIdx.x; q < (int)n; q += blockDim.x) {
-            P.tv[first + q] = tl.tv[q];
-            P.tvold[first + q] = tl.tvold[q];
-            P.tf[first + q] = tl.tf[q];
+        const TailLev &g = lvs[top];
+        for (int q = threadIdx.x; q < g.npad; q += blockDim.x) {
+            const T a = P.tv[first + g.off + q], c = P.tf[first + g.off + q];
+            sv[g.off + q] = a;
+            sf[g.off + q] = c;
         }
+        if (VAR)
+            for (int q = threadIdx.x; q < n; q += blockDim.x) se[q] = P.teps[first + q];
+        __syncthreads();
+        const Tail<T, D, VAR> tl{lvs, &bcs, red, sv, so, sf, VAR ? se : nullptr, P.tvold + first, top};
+        steps = tl.run(ops, nops, tp);
+        for (int q = threadIdx.x; q < g.npad; q += blockDim.x) P.tv[first + g.off + q] = sv[g.off + q];
+    } else {
+        __syncthreads();
+        const Tail<T, D, VAR> tl{lvs, &bcs, red, P.tv + first, P.tvold + first, P.tf + first,
+                                 VAR ? P.teps + first : nullptr, nullptr, top};
+        steps = tl.run(ops, nops, tp);
     }
     if (threadIdx.x == 0) steps_out[dm] = steps;
 }
@@ -1065,22 +1198,22 @@ __global__ void __launch_bounds__(512) k_tail_eps(Plane<T> P, DevTables tb, int 
     tail_span(tb, dm, nt - 1, D, &first);
     tail_setup(tb, dm, nt, D, first, lvs, &bcs);
     __syncthreads();
-    Tail<T, D, true> tl{lvs, &bcs, red, P.tv + first, P.tvold + first, P.tf + first, P.teps + first};
+    const Tail<T, D, true> tl{lvs, &bcs, red, P.tv + first, P.tvold + first, P.tf + first, P.teps + first,
+                              nullptr, nt - 1};
     for (int l = nt - 1; l >= 1; l--) {
-        const TailGeo &gf = tl.geo(l), &gc = tl.geo(l - 1);
-        const int n = tl.count(gc);
-        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        const TailLev &gf = lvs[l], &gc = lvs[l - 1];
+        for (int c = threadIdx.x; c < gc.ncell; c += blockDim.x) {
             int I, J, K;
             tl.cell(gc, c, I, J, K);
             T s = T(0);
             for (int q = 0; q < (1 << D); q++)
-                s += tl.teps[gf.idx(2 * I + (q & 1), 2 * J + ((q >> 1) & 1), D == 3 ? 2 * K + (q >> 2) : 0, D)];
-            tl.teps[gc.idx(I, J, K, D)] = s / T(1 << D);
+                s += tl.teps[tix<D>(gf, 2 * I + (q & 1), 2 * J + ((q >> 1) & 1), D == 3 ? 2 * K + (q >> 2) : 0)];
+            tl.teps[tix<D>(gc, I, J, K)] = s / T(1 << D);
         }
         __syncthreads();
     }
     for (int l = 0; l < nt; l++) {
-        tl.ghosts(l, tl.teps, true);
+        tl.fill_ghosts(l, tl.teps, true);
         __syncthreads();
     }
 }
@@ -1543,16 +1676,33 @@ void K<T>::correct(const Launch &L, const Plane<T> &P, int lev, int b0, int nb, 
     });
 }
 
+// The single-workgroup coarse solver keeps a domain's grids in up to this much LDS
+// (gfx950: 160 KB per workgroup; the rest holds the kernel's static arrays).
+constexpr int kTailLds = 150 * 1024;
+
+template <typename K>
+static void allow_lds(K kernel) {
+    hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, kTailLds);
+}
+
 template <typename T>
 void K<T>::tail(const Launch &L, const Plane<T> &P, int mode, uint64_t mask, const TailParams &tp, bool var) {
-    const int TPB = 512;
-    const int lds = 60 * 1024;
+    const int TPB = var ? 512 : 1024;   // the variable-coefficient code needs more registers
+    const int lds = kTailLds;
+    static bool once = [] {
+        allow_lds(k_tail<T, 3, true>);
+        allow_lds(k_tail<T, 3, false>);
+        allow_lds(k_tail<T, 2, true>);
+        allow_lds(k_tail<T, 2, false>);
+        return true;
+    }();
+    (void)once;
     if (L.dim == 3) {
-        if (var) k_tail<T, 3, true><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, L.nt, mode, mask, tp, L.coarse_steps, lds);
-        else k_tail<T, 3, false><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, L.nt, mode, mask, tp, L.coarse_steps, lds);
+        if (var) k_tail<T, 3, true><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, mode, mask, tp, L.coarse_steps, lds);
+        else k_tail<T, 3, false><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, mode, mask, tp, L.coarse_steps, lds);
     } else {
-        if (var) k_tail<T, 2, true><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, L.nt, mode, mask, tp, L.coarse_steps, lds);
-        else k_tail<T, 2, false><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, L.nt, mode, mask, tp, L.coarse_steps, lds);
+        if (var) k_tail<T, 2, true><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, mode, mask, tp, L.coarse_steps, lds);
+        else k_tail<T, 2, false><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, mode, mask, tp, L.coarse_steps, lds);
     }
 }
 

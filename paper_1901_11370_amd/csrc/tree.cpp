@@ -146,6 +146,23 @@ std::string build_tree(HostTree &T, const mg_domain *doms, int ndom, int bs, int
         T.doms.push_back(hd);
     }
 
+    // Small coarse levels go below the block levels: while every domain's lowest
+    // block level has at most kTailBig cells and lies below its base grid, that level
+    // becomes a uniform grid of the single-workgroup coarse solver.
+    for (;;) {
+        bool ok = true;
+        for (const HDomain &hd : T.doms) {
+            int64_t c = 1;
+            for (int a = 0; a < dim; a++) c *= (int64_t)hd.nblk_low[a] * bs;
+            if (c > kTailBig || hd.base <= nt) ok = false;
+        }
+        if (!ok) break;
+        nt++;
+        for (HDomain &hd : T.doms)
+            for (int a = 0; a < dim; a++) hd.nblk_low[a] *= 2;
+    }
+    T.nt = nt;
+
     Builder bld;
     bld.dim = dim; bld.bs = bs; bld.nt = nt; bld.doms = &T.doms;
     // Every block of the levels up to the base grid exists.
@@ -285,7 +302,7 @@ std::string build_tree(HostTree &T, const mg_domain *doms, int ndom, int bs, int
             for (int a = 0; a < dim; a++) {
                 int64_t n;
                 if (l >= nt) n = (int64_t)hd.nblk_low[a] * bs << (l - nt);
-                else n = (int64_t)hd.nblk_low[a] * (bs >> (nt - l));
+                else n = ((int64_t)hd.nblk_low[a] * bs) >> (nt - l);
                 T.ncell[((size_t)i * MAXLEV + l) * 3 + a] = (int32_t)n;
                 T.h[((size_t)i * MAXLEV + l) * 3 + a] = (hd.d.hi[a] - hd.d.lo[a]) / (double)n;
             }
@@ -315,6 +332,10 @@ std::string build_tree(HostTree &T, const mg_domain *doms, int ndom, int bs, int
             l--;
         }
         T.tail_top[i] = l;
+        int64_t c = 1;
+        for (int a = 0; a < dim; a++) c *= T.ncell[((size_t)i * MAXLEV + l) * 3 + a];
+        if (c >= (1 << 22)) return "coarse grid below the block levels too large (odd block counts)";
+        if (l > 14) return "too many coarse grid levels below the block levels";
     }
     return "";
 }
