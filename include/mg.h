@@ -85,6 +85,9 @@ typedef struct {
     int32_t variable_eps;     /* 0: eps = 1, constant-coefficient stencil; 1: eps field */
     int32_t ir_first_fmg;     /* mixed: the first refinement step runs an FP32 FMG cycle */
     int32_t ir_vcycles;       /* mixed: FP32 V-cycles per refinement step (>= 1) */
+    int32_t graphs;           /* 1 (default): each cycle sequence (V-cycle, FMG cycle,
+                                 refinement step, residual norm) is captured once as a
+                                 HIP graph and replayed; 0: kernels launched one by one */
 } mg_params;
 
 /* Fills p with the paper's defaults (Sec. 2.4) and FP64 precision. */

@@ -45,9 +45,15 @@ struct mg_tree {
     int64_t nb = 0, nleafblk = 0, nc = 0, ng = 0;
     // stats
     std::vector<double> stat_res, stat_sec;
-    // profiling
+    // captured cycle sequences (graph kind x homogeneous flag), replayed on `stream`
+    hipStream_t cap = nullptr;       // capture stream (non-blocking, default priority)
+    double *h_norms = nullptr;       // pinned host copy of the per-domain norms
+    hipGraphExec_t gexec[32] = {};
+    bool gfail[32] = {};
+    // profiling: event pairs around the finest-level smoothing launches (kernels are
+    // then launched one by one, not replayed from graphs)
     bool prof = false;
-    std::vector<hipEvent_t> ev;      // pairs (start, stop)
+    std::vector<hipEvent_t> ev;      // pool
     size_t ev_used = 0;
     int64_t prof_launches = 0;
     double prof_ms = 0.0;
@@ -268,11 +274,9 @@ struct Driver {
                         e0 = t->ev[t->ev_used];
                         e1 = t->ev[t->ev_used + 1];
                         t->ev_used += 2;
-                        (void)hipEventRecord(e0, L.stream);
                     }
                 }
-                K<T>::gsrb(L, P, l, lvb0(t, l), lvnb(t, l), c, m, v);
-                if (e1) (void)hipEventRecord(e1, L.stream);
+                K<T>::gsrb(L, P, l, lvb0(t, l), lvnb(t, l), c, m, v, e0, e1);
                 if (ncf) cf_refresh(l, m);
             }
     }
@@ -396,22 +400,73 @@ struct Driver {
 Driver<double> d64(mg_tree *t) { return Driver<double>{t, launch(t, t->homog), t->P64, var(t)}; }
 Driver<float> d32(mg_tree *t) { return Driver<float>{t, launch(t, true), t->P32, var(t)}; }
 
-// FP64 composite residual; r may be written into the FP32 right-hand side.
-int residual64(mg_tree *t, bool write_r32, std::vector<double> *norms) {
+// FP64 composite residual (per-domain norms in d_domnorms); r may be written into the
+// FP32 right-hand side; with copy_out the norms are copied to the pinned host buffer.
+void enq_residual(mg_tree *t, bool write_r32, bool copy_out) {
     Driver<double> D = d64(t);
     // Without refinement the leaf residual uses only same-level and boundary ghosts,
     // which every kernel keeps current; parents enter only through coarse-fine ghosts.
     if (t->T.refined) D.sync();
     launch_norm64(D.L, t->P64, (int)t->nleafblk, var(t), write_r32 ? t->P32.f : nullptr, nullptr);
     launch_reduce_norms(D.L);
-    int rc = check_launch(t);
-    if (rc) return rc;
-    if (norms) {
-        norms->assign(4 * t->T.ndom, 0.0);
-        HIP_OR_FAIL(t, hipMemcpyAsync(norms->data(), t->d_domnorms, norms->size() * 8, hipMemcpyDeviceToHost, t->stream));
-        HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));
-    }
+    if (copy_out)
+        (void)hipMemcpyAsync(t->h_norms, t->d_domnorms, 4 * (size_t)t->T.ndom * 8, hipMemcpyDeviceToHost, t->stream);
+}
+
+// Waits for the stream and returns the norms copied by the last enq_residual.
+int read_norms(mg_tree *t, std::vector<double> *norms) {
+    HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));
+    norms->assign(t->h_norms, t->h_norms + 4 * t->T.ndom);
     return MG_OK;
+}
+
+// Kinds of captured sequences.
+enum {
+    G_V = 0, G_FMG, G_V_NORM, G_FMG_NORM, G_NORM, G_NORM_R32, G_IRV_NORM, G_IRFMG_NORM, G_IRV_FULL, G_IRFMG_FULL,
+    G_KINDS
+};
+
+void drop_graphs(mg_tree *t) {
+    for (auto &g : t->gexec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+    for (bool &f : t->gfail) f = false;
+}
+
+// Queues body()'s kernels on the bound stream: replays the captured graph of this
+// kind (capturing it on first use), or launches directly when graphs are off, while
+// profiling, or if capture failed.
+template <typename F>
+int run_seq(mg_tree *t, int kind, F &&body) {
+    const int key = 2 * kind + (t->homog ? 1 : 0);
+    if (t->prm.graphs && !t->prof && !t->gfail[key]) {
+        if (!t->gexec[key]) {
+            hipStream_t user = t->stream;
+            bool ok = hipStreamBeginCapture(t->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            hipGraph_t g = nullptr;
+            if (ok) {
+                t->stream = t->cap;
+                body();
+                t->stream = user;
+                ok = hipStreamEndCapture(t->cap, &g) == hipSuccess && g;
+                ok = ok && hipGetLastError() == hipSuccess;
+            }
+            if (ok) ok = hipGraphInstantiate(&t->gexec[key], g, nullptr, nullptr, 0) == hipSuccess;
+            if (g) (void)hipGraphDestroy(g);
+            if (!ok) {
+                t->gexec[key] = nullptr;
+                t->gfail[key] = true;
+                (void)hipGetLastError();
+            }
+        }
+        if (t->gexec[key]) {
+            HIP_OR_FAIL(t, hipGraphLaunch(t->gexec[key], t->stream));
+            return MG_OK;
+        }
+    }
+    body();
+    return check_launch(t);
 }
 
 void rel_norms(const mg_tree *t, const std::vector<double> &n, double *mx, double *l2) {
@@ -440,7 +495,7 @@ int worst(const mg_tree *t, const std::vector<double> &n, double *mx, double *l2
 // One step of iterative refinement: r = f - L phi in FP64 (also the norm), then the
 // FP32 correction solve L e = r with zero initial guess and homogeneous boundary
 // values, then phi += e on the leaves.
-int ir_correction(mg_tree *t, bool use_fmg) {
+void ir_enqueue(mg_tree *t, bool use_fmg) {
     Driver<float> D = d32(t);
     const Plane<float> &P = t->P32;
     K<float>::zero(D.L, P.v, (size_t)(t->nb * t->nc));
@@ -453,7 +508,6 @@ int ir_correction(mg_tree *t, bool use_fmg) {
     }
     Launch L64 = launch(t, t->homog);
     launch_add_leaf(L64, t->P64.v, t->P64.vg, P.v, (int)t->nleafblk);
-    return check_launch(t);
 }
 
 int require_bound(mg_tree *t) {
@@ -496,6 +550,7 @@ int mg_default_params(mg_params *p) {
     p->variable_eps = 0;
     p->ir_first_fmg = 1;
     p->ir_vcycles = 1;
+    p->graphs = 1;
     return MG_OK;
 }
 
@@ -508,7 +563,7 @@ int mg_tree_create(const mg_domain *domains, int n_domains, int block_size, int 
     else mg_default_params(&t->prm);
     const mg_params &p = t->prm;
     if (p.n_down < 0 || p.n_up < 0 || p.n_max_coarse < 1 || p.coarse_rel_tol < 0 || p.coarse_abs_tol < 0 ||
-        (p.precision != MG_FP64 && p.precision != MG_MIXED) || p.ir_vcycles < 1) {
+        (p.precision != MG_FP64 && p.precision != MG_MIXED) || p.ir_vcycles < 1 || (p.graphs != 0 && p.graphs != 1)) {
         delete t;
         return MG_ERR_ARG;
     }
@@ -525,6 +580,9 @@ int mg_tree_create(const mg_domain *domains, int n_domains, int block_size, int 
 void mg_tree_destroy(mg_tree *t) {
     if (!t) return;
     for (hipEvent_t e : t->ev) (void)hipEventDestroy(e);
+    drop_graphs(t);
+    if (t->cap) (void)hipStreamDestroy(t->cap);
+    if (t->h_norms) (void)hipHostFree(t->h_norms);
     delete t;
 }
 
@@ -538,6 +596,12 @@ int mg_tree_bind(mg_tree *t, void *device_store, size_t bytes, void *hip_stream)
     if (!t || !device_store) return MG_ERR_ARG;
     if (((uintptr_t)device_store) & 255) return fail(t, MG_ERR_ARG, "store must be 256-byte aligned");
     if (bytes < t->need) return fail(t, MG_ERR_OOM, "store has %zu bytes, %zu needed", bytes, t->need);
+    drop_graphs(t);
+    if (!t->cap) {
+        prepare_kernels();
+        HIP_OR_FAIL(t, hipStreamCreateWithFlags(&t->cap, hipStreamNonBlocking));
+    }
+    if (!t->h_norms) HIP_OR_FAIL(t, hipHostMalloc((void **)&t->h_norms, 4 * (size_t)t->T.ndom * 8, hipHostMallocDefault));
     t->store = (char *)device_store;
     t->stream = (hipStream_t)hip_stream;
     plan(t, t->store);
@@ -692,11 +756,14 @@ int mg_vcycle(mg_tree *t, int n) {
     if (n < 0) return MG_ERR_ARG;
     for (int c = 0; c < n; c++) {
         if (mixed(t)) {
-            if ((rc = residual64(t, true, nullptr))) return rc;
-            if ((rc = ir_correction(t, false))) return rc;
+            rc = run_seq(t, G_IRV_FULL, [&] {
+                enq_residual(t, true, false);
+                ir_enqueue(t, false);
+            });
         } else {
-            d64(t).vcycle(t->T.nlev - 1, all_mask(t));
+            rc = run_seq(t, G_V, [&] { d64(t).vcycle(t->T.nlev - 1, all_mask(t)); });
         }
+        if (rc) return rc;
     }
     return check_launch(t);
 }
@@ -707,11 +774,14 @@ int mg_fmg(mg_tree *t, int n) {
     if (n < 0) return MG_ERR_ARG;
     for (int c = 0; c < n; c++) {
         if (mixed(t)) {
-            if ((rc = residual64(t, true, nullptr))) return rc;
-            if ((rc = ir_correction(t, true))) return rc;
+            rc = run_seq(t, G_IRFMG_FULL, [&] {
+                enq_residual(t, true, false);
+                ir_enqueue(t, true);
+            });
         } else {
-            d64(t).fmg();
+            rc = run_seq(t, G_FMG, [&] { d64(t).fmg(); });
         }
+        if (rc) return rc;
     }
     return check_launch(t);
 }
@@ -721,7 +791,8 @@ int mg_domain_residual_norms(mg_tree *t, double *max_rel, double *l2_rel) {
     if (rc) return rc;
     if (!max_rel || !l2_rel) return MG_ERR_ARG;
     std::vector<double> n;
-    if ((rc = residual64(t, false, &n))) return rc;
+    if ((rc = run_seq(t, G_NORM, [&] { enq_residual(t, false, true); }))) return rc;
+    if ((rc = read_norms(t, &n))) return rc;
     rel_norms(t, n, max_rel, l2_rel);
     return MG_OK;
 }
@@ -730,7 +801,8 @@ int mg_residual_norm(mg_tree *t, double *max_rel, double *l2_rel) {
     int rc = require_bound(t);
     if (rc) return rc;
     std::vector<double> n;
-    if ((rc = residual64(t, false, &n))) return rc;
+    if ((rc = run_seq(t, G_NORM, [&] { enq_residual(t, false, true); }))) return rc;
+    if ((rc = read_norms(t, &n))) return rc;
     return worst(t, n, max_rel, l2_rel);
 }
 
@@ -748,28 +820,48 @@ int mg_solve(mg_tree *t, double rel_tol, int max_cycles, int use_fmg_first, int 
     int cycles = 0;
     double rel = INFINITY;
     std::vector<double> n;
+    // Each step queues one captured sequence: the cycle followed by the residual norms
+    // (copied to the host), then the host reads the norms and decides.
+    const uint64_t all = all_mask(t);
+    const int top = t->T.nlev - 1;
     if (!mixed(t)) {
         if (use_fmg_first && max_cycles > 0) {
-            d64(t).fmg();
+            rc = run_seq(t, G_FMG_NORM, [&] {
+                d64(t).fmg();
+                enq_residual(t, false, true);
+            });
             cycles++;
+        } else {
+            rc = run_seq(t, G_NORM, [&] { enq_residual(t, false, true); });
         }
+        if (rc) return rc;
         for (;;) {
-            if ((rc = residual64(t, false, &n))) return rc;
+            if ((rc = read_norms(t, &n))) return rc;
             rc = worst(t, n, &rel, nullptr);
             record(rel);
             if (rc) break;
             if (rel <= rel_tol || cycles >= max_cycles) break;
-            d64(t).vcycle(t->T.nlev - 1, all_mask(t));
+            if ((rc = run_seq(t, G_V_NORM, [&] {
+                     d64(t).vcycle(top, all);
+                     enq_residual(t, false, true);
+                 })))
+                return rc;
             cycles++;
         }
     } else {
+        if ((rc = run_seq(t, G_NORM_R32, [&] { enq_residual(t, true, true); }))) return rc;
         for (;;) {
-            if ((rc = residual64(t, true, &n))) return rc;
+            if ((rc = read_norms(t, &n))) return rc;
             rc = worst(t, n, &rel, nullptr);
             record(rel);
             if (rc) break;
             if (rel <= rel_tol || cycles >= max_cycles) break;
-            if ((rc = ir_correction(t, cycles == 0 && use_fmg_first && t->prm.ir_first_fmg))) return rc;
+            const bool f = cycles == 0 && use_fmg_first && t->prm.ir_first_fmg;
+            if ((rc = run_seq(t, f ? G_IRFMG_NORM : G_IRV_NORM, [&] {
+                     ir_enqueue(t, f);
+                     enq_residual(t, true, true);
+                 })))
+                return rc;
             cycles++;
         }
     }

@@ -81,7 +81,7 @@ struct Launch {
 template <typename T>
 struct K {
     static void gsrb(const Launch &L, const Plane<T> &P, int lev, int b0, int nb, int colour,
-                     uint64_t mask, bool var);
+                     uint64_t mask, bool var, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
     static void ghost(const Launch &L, const Plane<T> &P, int b0, int nb, const int32_t *list,
                       int nlist, uint64_t mask, bool eps_field, bool cf_only);
     static void restrict_down(const Launch &L, const Plane<T> &P, int lev, int b0, int nb,
@@ -107,6 +107,10 @@ struct K {
 
 enum { RESTRICT_FAS = 0, RESTRICT_V = 1, RESTRICT_EPS = 2 };
 enum { TAIL_VCYCLE = 0, TAIL_FMG = 1 };
+
+// Kernel attributes set once per process before any launch (large dynamic LDS of the
+// coarse-grid kernel).
+void prepare_kernels();
 
 // FP64 composite residual over the leaf blocks; optionally writes r (cast) into rout.
 void launch_norm64(const Launch &L, const Plane<double> &P, int nleafblk, bool var, float *rout32,

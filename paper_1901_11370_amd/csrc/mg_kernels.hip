@@ -7,6 +7,8 @@
 // All kernels are bandwidth-bound stencils (about one flop per byte), so they use no
 // matrix cores.  Blocks store their interior split by colour so that a half-sweep
 // reads only the other colour and writes only its own, with unit-stride access.
+#include <hip/hip_ext.h>
+
 #include <cmath>
 #include <cstdio>
 
@@ -1610,15 +1612,25 @@ static inline int cells(int dim, int bs) { return dim == 3 ? bs * bs * bs : bs *
         }                                                                     \
     } while (0)
 
+// With events, the launch records the kernel's own start and end (no extra packets).
 template <typename T>
 void K<T>::gsrb(const Launch &L, const Plane<T> &P, int lev, int b0, int nb, int colour, uint64_t mask,
-                bool var) {
+                bool var, hipEvent_t ev0, hipEvent_t ev1) {
     if (nb <= 0) return;
     DISPATCH_DB(L, {
         constexpr int NH = G<D, BS>::NH;
         constexpr int TPB = NH < 256 ? NH : 256;
-        if (var) k_gsrb<T, D, BS, true><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
-        else k_gsrb<T, D, BS, false><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+        if (ev0) {
+            if (var)
+                hipExtLaunchKernelGGL((k_gsrb<T, D, BS, true>), dim3(nb), dim3(TPB), 0, L.stream, ev0, ev1, 0, P, L.tb,
+                                      lev, b0, colour, mask);
+            else
+                hipExtLaunchKernelGGL((k_gsrb<T, D, BS, false>), dim3(nb), dim3(TPB), 0, L.stream, ev0, ev1, 0, P, L.tb,
+                                      lev, b0, colour, mask);
+        } else {
+            if (var) k_gsrb<T, D, BS, true><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+            else k_gsrb<T, D, BS, false><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+        }
     });
 }
 
@@ -1685,18 +1697,21 @@ static void allow_lds(K kernel) {
     hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, kTailLds);
 }
 
+void prepare_kernels() {
+    allow_lds(k_tail<double, 3, true>);
+    allow_lds(k_tail<double, 3, false>);
+    allow_lds(k_tail<double, 2, true>);
+    allow_lds(k_tail<double, 2, false>);
+    allow_lds(k_tail<float, 3, true>);
+    allow_lds(k_tail<float, 3, false>);
+    allow_lds(k_tail<float, 2, true>);
+    allow_lds(k_tail<float, 2, false>);
+}
+
 template <typename T>
 void K<T>::tail(const Launch &L, const Plane<T> &P, int mode, uint64_t mask, const TailParams &tp, bool var) {
     const int TPB = var ? 512 : 1024;   // the variable-coefficient code needs more registers
     const int lds = kTailLds;
-    static bool once = [] {
-        allow_lds(k_tail<T, 3, true>);
-        allow_lds(k_tail<T, 3, false>);
-        allow_lds(k_tail<T, 2, true>);
-        allow_lds(k_tail<T, 2, false>);
-        return true;
-    }();
-    (void)once;
     if (L.dim == 3) {
         if (var) k_tail<T, 3, true><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, mode, mask, tp, L.coarse_steps, lds);
         else k_tail<T, 3, false><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, mode, mask, tp, L.coarse_steps, lds);
