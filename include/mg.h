@@ -13,7 +13,9 @@
  *    the last error of a tree is available from mg_last_error().
  *  - Ownership: the caller owns every array it passes and the device store it binds
  *    (one allocation of mg_tree_storage_bytes() bytes, 256-byte aligned); the library
- *    owns the tree's host metadata and never allocates device memory.
+ *    owns the tree's host metadata, never allocates device memory for data, and at
+ *    bind creates one non-blocking stream (to capture HIP graphs) and a small pinned
+ *    host buffer (residual norms).
  *  - Leaf order: domain, then refinement level (coarse to fine), then Morton order of
  *    the block coordinates on that level, then cells with x fastest (then y, then z).
  *  - Device work is asynchronous on the stream given to mg_tree_bind().  Calls that
@@ -88,6 +90,13 @@ typedef struct {
     int32_t graphs;           /* 1 (default): each cycle sequence (V-cycle, FMG cycle,
                                  refinement step, residual norm) is captured once as a
                                  HIP graph and replayed; 0: kernels launched one by one */
+    int32_t krylov;           /* mixed only.  0 (default): the refinement steps are plain
+                                 (phi += e, e from FP32 cycles).  m >= 1: mg_solve runs
+                                 FGMRES(m) in FP64 on the correction equation with the FP32
+                                 cycles as the (flexible) preconditioner, one FP64 residual
+                                 and update per restart; needs (2m + 1) FP64 leaf vectors in
+                                 the store.  For coefficients with large jumps, where the
+                                 plain cycles stall.  At most 64. */
 } mg_params;
 
 /* Fills p with the paper's defaults (Sec. 2.4) and FP64 precision. */
@@ -150,8 +159,11 @@ int mg_domain_residual_norms(mg_tree *t, double *max_rel, double *l2_rel);
 
 /* Solve to max-norm relative residual <= rel_tol: optional FMG first, then V-cycles
  * (FP64), or FP64 iterative refinement around FP32 cycles (MG_MIXED), checking the
- * norm after every cycle / refinement step.  cycles_done may be NULL.  Returns
- * MG_ERR_NOT_CONVERGED if max_cycles is reached first. */
+ * norm after every cycle / refinement step.  With MG_MIXED and params.krylov = m > 0
+ * the refinement is FGMRES(m) (flexible GMRES, restarted every m steps or when its
+ * residual estimate falls by 1e-6; the true FP64 residual is checked at each restart);
+ * one FP32 preconditioning solve counts as a cycle.  cycles_done may be NULL.
+ * Returns MG_ERR_NOT_CONVERGED if max_cycles is reached first. */
 int mg_solve(mg_tree *t, double rel_tol, int max_cycles, int use_fmg_first, int *cycles_done);
 /* Per-check record of the last mg_solve: relative residual and seconds since start. */
 int mg_solve_stats(const mg_tree *t, int max_records, double *rel_residual, double *seconds,

@@ -39,6 +39,10 @@ struct mg_tree {
     double *d_stage = nullptr, *d_stage2 = nullptr;
     int32_t *d_steps = nullptr;
     double *d_partials = nullptr, *d_domnorms = nullptr;
+    // FGMRES (mixed mode with krylov = m): V[m+1], Z[m] leaf vectors, inner-product
+    // partials, dot results (3 sets), combination coefficients; pinned host copies
+    double *d_kv = nullptr, *d_kz = nullptr, *d_kpart = nullptr, *d_kdots = nullptr, *d_ky = nullptr;
+    double *h_k = nullptr;
     size_t off_tables = 0, bytes_tables = 0;
     std::vector<char> host_tables;  // image of the table region
     // layout bookkeeping
@@ -205,7 +209,23 @@ size_t plan(mg_tree *t, char *base) {
     size_t o_st = L.take<double>(T.nleaf_cells), o_st2 = L.take<double>(T.nleaf_cells);
     size_t o_steps = L.take<int32_t>(T.ndom), o_part = L.take<double>(4 * std::max<int64_t>(t->nleafblk, 1));
     size_t o_dn = L.take<double>(4 * T.ndom);
+    const int km = mixed(t) ? t->prm.krylov : 0;
+    size_t o_kv = 0, o_kz = 0, o_kp = 0, o_kd = 0, o_ky = 0;
+    if (km > 0) {
+        o_kv = L.take<double>((size_t)(km + 1) * T.nleaf_cells);
+        o_kz = L.take<double>((size_t)km * T.nleaf_cells);
+        o_kp = L.take<double>((size_t)(km + 1) * dots_chunks(T.nleaf_cells));
+        o_kd = L.take<double>(3 * (size_t)(km + 1));
+        o_ky = L.take<double>((size_t)(km + 1));
+    }
     if (base) {
+        if (km > 0) {
+            t->d_kv = (double *)P(o_kv);
+            t->d_kz = (double *)P(o_kz);
+            t->d_kpart = (double *)P(o_kp);
+            t->d_kdots = (double *)P(o_kd);
+            t->d_ky = (double *)P(o_ky);
+        }
         t->d_stage = (double *)P(o_st);
         t->d_stage2 = (double *)P(o_st2);
         t->d_steps = (int32_t *)P(o_steps);
@@ -510,6 +530,135 @@ void ir_enqueue(mg_tree *t, bool use_fmg) {
     launch_add_leaf(L64, t->P64.v, t->P64.vg, P.v, (int)t->nleafblk);
 }
 
+// ---- FGMRES refinement (mixed mode, krylov = m)
+// r = f - L phi (FP64, actual boundary values) into the leaf vector out; norms copied
+// to the host buffer.
+void enq_residual_vec(mg_tree *t, double *out) {
+    Driver<double> D = d64(t);
+    if (t->T.refined) D.sync();
+    launch_norm64(D.L, t->P64, (int)t->nleafblk, var(t), nullptr, out);
+    launch_reduce_norms(D.L);
+    (void)hipMemcpyAsync(t->h_norms, t->d_domnorms, 4 * (size_t)t->T.ndom * 8, hipMemcpyDeviceToHost, t->stream);
+}
+
+// w = A z, A the composite operator with homogeneous boundary values; z is placed in
+// the v_old field of the FP64 plane (unused by mixed-mode solves).
+void enq_apply(mg_tree *t, double *z, double *w) {
+    Plane<double> Q = t->P64;
+    Q.v = t->P64.vold;
+    Q.vg = t->P64.voldg;
+    Q.f = nullptr;
+    Driver<double> D{t, launch(t, true), Q, var(t)};
+    launch_vec_blocks<double>(D.L, Q.v, z, (int)t->nleafblk, true);
+    if (t->T.refined) D.sync();
+    else
+        for (int l = t->T.nt; l < t->T.nlev; l++) D.ghost_level(l, all_mask(t));
+    launch_norm64(D.L, Q, (int)t->nleafblk, var(t), nullptr, w);
+}
+
+// z = M^-1 v: FP32 cycles (ir_vcycles V-cycles from zero, homogeneous boundary values)
+// on the correction equation with right-hand side v.
+void enq_precond(mg_tree *t, double *v, double *z) {
+    Driver<float> D = d32(t);
+    const Plane<float> &P = t->P32;
+    launch_vec_blocks<float>(D.L, P.f, v, (int)t->nleafblk, true);
+    K<float>::zero(D.L, P.v, (size_t)(t->nb * t->nc));
+    K<float>::zero(D.L, P.vg, (size_t)(t->nb * t->ng));
+    K<float>::zero(D.L, P.tv, (size_t)t->T.tail_cells);
+    for (int c = 0; c < std::max(1, t->prm.ir_vcycles); c++) D.vcycle(t->T.nlev - 1, all_mask(t));
+    launch_vec_blocks<float>(D.L, P.v, z, (int)t->nleafblk, false);
+}
+
+// Restarted flexible GMRES on A e = r in FP64 (classical Gram-Schmidt with one
+// re-orthogonalisation pass, Givens rotations), preconditioned by enq_precond; each
+// restart starts from the true residual of the current phi and ends with phi += Z y.
+template <typename Rec>
+int solve_fgmres(mg_tree *t, double rel_tol, int max_cycles, bool fmg_first, int *cycles_io, double *rel_out,
+                 Rec &&record) {
+    const int m = t->prm.krylov;
+    const int64_t n = t->T.nleaf_cells;
+    const int nlb = (int)t->nleafblk;
+    double *V = t->d_kv, *Z = t->d_kz, *part = t->d_kpart, *dd = t->d_kdots;
+    auto Vi = [&](int i) { return V + (int64_t)i * n; };
+    auto Zi = [&](int i) { return Z + (int64_t)i * n; };
+    const Launch L = launch(t, true);
+    const size_t stride3 = (size_t)(m + 1);
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), g(m + 1), cs(m), sn(m), y(m);
+    auto h = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+    std::vector<double> nrm;
+    int &cycles = *cycles_io;
+    int rc;
+    for (;;) {
+        enq_residual_vec(t, Vi(0));
+        if ((rc = read_norms(t, &nrm))) return rc;
+        rc = worst(t, nrm, rel_out, nullptr);
+        record(*rel_out);
+        if (rc) return rc;
+        if (*rel_out <= rel_tol || cycles >= max_cycles) return MG_OK;
+        if (cycles == 0 && fmg_first && t->prm.ir_first_fmg) {
+            // first step: a plain refinement step with an FP32 FMG cycle
+            launch_vec_blocks<float>(L, t->P32.f, Vi(0), nlb, true);
+            ir_enqueue(t, true);
+            cycles++;
+            continue;
+        }
+        launch_dots(L, Vi(0), n, 1, Vi(0), n, part, dd);
+        HIP_OR_FAIL(t, hipMemcpyAsync(t->h_k, dd, 8, hipMemcpyDeviceToHost, t->stream));
+        HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));
+        const double beta = std::sqrt(t->h_k[0]);
+        if (!std::isfinite(beta)) return fail(t, MG_ERR_NAN, "residual is not finite");
+        if (beta == 0.0) return MG_OK;
+        launch_scale(L, Vi(0), 1.0 / beta, n);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m && cycles < max_cycles; j++) {
+            enq_precond(t, Vi(j), Zi(j));
+            cycles++;
+            enq_apply(t, Zi(j), Vi(j + 1));
+            launch_dots(L, V, n, j + 1, Vi(j + 1), n, part, dd);
+            launch_combo(L, Vi(j + 1), V, n, dd, j + 1, -1.0, false, n);
+            launch_dots(L, V, n, j + 1, Vi(j + 1), n, part, dd + stride3);
+            launch_combo(L, Vi(j + 1), V, n, dd + stride3, j + 1, -1.0, false, n);
+            launch_dots(L, Vi(j + 1), n, 1, Vi(j + 1), n, part, dd + 2 * stride3);
+            if ((rc = check_launch(t))) return rc;
+            HIP_OR_FAIL(t, hipMemcpyAsync(t->h_k, dd, 3 * stride3 * 8, hipMemcpyDeviceToHost, t->stream));
+            HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));
+            for (int i = 0; i <= j; i++) h(i, j) = t->h_k[i] + t->h_k[stride3 + i];
+            const double hn = std::sqrt(t->h_k[2 * stride3]);
+            if (!std::isfinite(hn)) return fail(t, MG_ERR_NAN, "Krylov vector is not finite");
+            h(j + 1, j) = hn;
+            for (int i = 0; i < j; i++) {
+                const double a = h(i, j), b = h(i + 1, j);
+                h(i, j) = cs[i] * a + sn[i] * b;
+                h(i + 1, j) = -sn[i] * a + cs[i] * b;
+            }
+            const double den = std::hypot(h(j, j), h(j + 1, j));
+            cs[j] = den > 0 ? h(j, j) / den : 1.0;
+            sn[j] = den > 0 ? h(j + 1, j) / den : 0.0;
+            h(j, j) = den;
+            h(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            if (hn == 0.0 || std::fabs(g[j + 1]) <= 1e-6 * beta) break;
+            launch_scale(L, Vi(j + 1), 1.0 / hn, n);
+        }
+        if (k == 0) return MG_OK;
+        for (int i = k - 1; i >= 0; i--) {
+            double s = g[i];
+            for (int q = i + 1; q < k; q++) s -= h(i, q) * y[q];
+            y[i] = h(i, i) != 0.0 ? s / h(i, i) : 0.0;
+        }
+        double *hy = t->h_k + 3 * stride3;
+        for (int i = 0; i < k; i++) hy[i] = y[i];
+        HIP_OR_FAIL(t, hipMemcpyAsync(t->d_ky, hy, (size_t)k * 8, hipMemcpyHostToDevice, t->stream));
+        launch_combo(L, Vi(0), Z, n, t->d_ky, k, 1.0, true, n);
+        launch_add_vec(launch(t, t->homog), t->P64.v, t->P64.vg, Vi(0), nlb);
+        if ((rc = check_launch(t))) return rc;
+    }
+}
+
 int require_bound(mg_tree *t) {
     if (!t) return MG_ERR_ARG;
     if (!t->bound) return fail(t, MG_ERR_STATE, "tree is not bound to a device store");
@@ -551,6 +700,7 @@ int mg_default_params(mg_params *p) {
     p->ir_first_fmg = 1;
     p->ir_vcycles = 1;
     p->graphs = 1;
+    p->krylov = 0;
     return MG_OK;
 }
 
@@ -563,7 +713,8 @@ int mg_tree_create(const mg_domain *domains, int n_domains, int block_size, int 
     else mg_default_params(&t->prm);
     const mg_params &p = t->prm;
     if (p.n_down < 0 || p.n_up < 0 || p.n_max_coarse < 1 || p.coarse_rel_tol < 0 || p.coarse_abs_tol < 0 ||
-        (p.precision != MG_FP64 && p.precision != MG_MIXED) || p.ir_vcycles < 1 || (p.graphs != 0 && p.graphs != 1)) {
+        (p.precision != MG_FP64 && p.precision != MG_MIXED) || p.ir_vcycles < 1 || (p.graphs != 0 && p.graphs != 1) ||
+        p.krylov < 0 || p.krylov > 64 || (p.krylov > 0 && p.precision != MG_MIXED)) {
         delete t;
         return MG_ERR_ARG;
     }
@@ -583,6 +734,7 @@ void mg_tree_destroy(mg_tree *t) {
     drop_graphs(t);
     if (t->cap) (void)hipStreamDestroy(t->cap);
     if (t->h_norms) (void)hipHostFree(t->h_norms);
+    if (t->h_k) (void)hipHostFree(t->h_k);
     delete t;
 }
 
@@ -602,6 +754,8 @@ int mg_tree_bind(mg_tree *t, void *device_store, size_t bytes, void *hip_stream)
         HIP_OR_FAIL(t, hipStreamCreateWithFlags(&t->cap, hipStreamNonBlocking));
     }
     if (!t->h_norms) HIP_OR_FAIL(t, hipHostMalloc((void **)&t->h_norms, 4 * (size_t)t->T.ndom * 8, hipHostMallocDefault));
+    if (!t->h_k && mixed(t) && t->prm.krylov > 0)
+        HIP_OR_FAIL(t, hipHostMalloc((void **)&t->h_k, 4 * (size_t)(t->prm.krylov + 1) * 8, hipHostMallocDefault));
     t->store = (char *)device_store;
     t->stream = (hipStream_t)hip_stream;
     plan(t, t->store);
@@ -847,6 +1001,11 @@ int mg_solve(mg_tree *t, double rel_tol, int max_cycles, int use_fmg_first, int 
                  })))
                 return rc;
             cycles++;
+        }
+    } else if (t->prm.krylov > 0) {
+        if ((rc = solve_fgmres(t, rel_tol, max_cycles, use_fmg_first != 0, &cycles, &rel, record))) {
+            if (cycles_done) *cycles_done = cycles;
+            return rc;
         }
     } else {
         if ((rc = run_seq(t, G_NORM_R32, [&] { enq_residual(t, true, true); }))) return rc;

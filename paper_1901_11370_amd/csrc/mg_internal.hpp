@@ -117,6 +117,18 @@ void launch_norm64(const Launch &L, const Plane<double> &P, int nleafblk, bool v
                    double *rout64);
 void launch_reduce_norms(const Launch &L);
 void launch_add_leaf(const Launch &L, double *v64, double *vg64, const float *v32, int nleafblk);
+// Krylov support on leaf vectors (rank-major: x[rank * cells_per_block + t]).
+void launch_add_vec(const Launch &L, double *v64, double *vg64, const double *vec, int nleafblk);
+template <typename S>
+void launch_vec_blocks(const Launch &L, S *blk, double *vec, int nleafblk, bool to_blocks);
+int dots_chunks(int64_t n);
+// out[i] = <V_i, w> for i < k (V_i = V + i * stride); partial holds k * dots_chunks(n).
+void launch_dots(const Launch &L, const double *V, int64_t stride, int k, const double *w, int64_t n,
+                 double *partial, double *out);
+// y = (overwrite ? 0 : y) + sign * sum_i coef[i] V_i (coef in device memory).
+void launch_combo(const Launch &L, double *y, const double *V, int64_t stride, const double *coef, int k, double sign,
+                  bool overwrite, int64_t n);
+void launch_scale(const Launch &L, double *x, double a, int64_t n);
 void launch_face_gradient(const Launch &L, const Plane<double> &P, const double *lam_blocks,
                           const double *lam_g, double *out_leaf, int nleafblk);
 

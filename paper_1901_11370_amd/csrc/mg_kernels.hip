@@ -1430,7 +1430,9 @@ __device__ __forceinline__ void block_reduce4(double &mr, double &sr, double &mf
 
 // Composite residual r = f - L v on every leaf block (FP64), with per-block partial
 // max |r|, sum vol r^2, max |f|, sum vol f^2; optionally writes r into the leaf
-// blocks of an output field (the right-hand side of an FP32 correction solve).
+// blocks of an output field (the right-hand side of an FP32 correction solve) or into
+// a leaf vector (rank-major, see the Krylov section).  Without f (P.f null) the
+// vector receives L v instead: the operator applied to v.
 // One workgroup per leaf block, v with its ghosts staged in LDS.
 template <int D, int BS, bool VAR>
 __global__ void __launch_bounds__(256) k_norm(Plane<double> P, DevTables tb, double *partials,
@@ -1451,7 +1453,7 @@ __global__ void __launch_bounds__(256) k_norm(Plane<double> P, DevTables tb, dou
 #pragma unroll
     for (int m = 0; m < IT; m++) {
         const int t = tid + m * TPB;
-        fr[m] = P.f[b * g::NC + (g::NC % TPB == 0 || t < g::NC ? t : 0)];
+        fr[m] = P.f ? P.f[b * g::NC + (g::NC % TPB == 0 || t < g::NC ? t : 0)] : 0.0;
     }
     const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
     const double h0 = hh[0], h1 = hh[1], h2 = hh[2];
@@ -1503,7 +1505,7 @@ __global__ void __launch_bounds__(256) k_norm(Plane<double> P, DevTables tb, dou
         sr += vol * r * r;
         sf += vol * fv * fv;
         if (rout32) rout32[b * g::NC + t] = (float)r;
-        if (rout64) rout64[b * g::NC + t] = r;
+        if (rout64) rout64[rank * g::NC + t] = P.f ? r : lv;
     }
     block_reduce4<TPB>(mr, sr, mf, sf);
     if (tid == 0) {
@@ -1542,20 +1544,22 @@ __global__ void __launch_bounds__(256) k_reduce_norms(DevTables tb, const double
 
 // v64 += v32 on every leaf block (the FP64 update of iterative refinement), with the
 // same-level and boundary ghosts of the FP64 field pushed.
-template <int D, int BS>
-__global__ void __launch_bounds__(256) k_add_leaf(double *v64, double *vg64, const float *v32, DevTables tb,
+// (The source is FP32 block storage, or an FP64 leaf vector when VEC.)
+template <int D, int BS, typename S, bool VEC>
+__global__ void __launch_bounds__(256) k_add_leaf(double *v64, double *vg64, const S *src, DevTables tb,
                                                   int wg_per_block) {
     using g = G<D, BS>;
-    const int64_t b = tb.leaf_blk[blockIdx.x / wg_per_block];
+    const int64_t rank = blockIdx.x / wg_per_block;
+    const int64_t b = tb.leaf_blk[rank];
     const int t = (blockIdx.x % wg_per_block) * blockDim.x + threadIdx.x;
     if (t >= g::NC) return;
-    const int dm = tb.dom[b];
-    const double *hh = tb.h + ((size_t)dm * MAXLEV + tb.lev[b]) * 3;
-    const double nv = v64[b * g::NC + t] + (double)v32[b * g::NC + t];
+    BlockCtx<D> cx;
+    cx.load(tb, b, tb.lev[b]);
+    const double nv = v64[b * g::NC + t] + (double)src[(VEC ? rank : b) * g::NC + t];
     v64[b * g::NC + t] = nv;
     int i, j, k;
     g::decode(t, i, j, k);
-    push_ghosts<double, D, BS>(vg64, tb, b, dm, hh, i, j, k, nv);
+    push_ghosts<double, D, BS>(vg64, cx, b, i, j, k, nv);
 }
 
 // dJ/deps per leaf cell from phi (v plane, ghosts filled) and lambda (blocks + ghosts).
@@ -1598,6 +1602,82 @@ __global__ void __launch_bounds__(256) k_face_grad(Plane<double> P, DevTables tb
 #define HIPCHK(x) (x)
 
 static inline int cells(int dim, int bs) { return dim == 3 ? bs * bs * bs : bs * bs; }
+
+// ------------------------------------------------------- Krylov vector kernels
+// Vectors over the leaf cells are stored rank-major: x[rank * NC + t], rank the leaf
+// block's position in leaf order and t the cell's position in the block's
+// colour-split storage (a fixed permutation of the leaf order, which inner products
+// and linear combinations do not see).
+template <typename S, int D, int BS, bool TO_BLOCKS>
+__global__ void __launch_bounds__(256) k_vec_blocks(S *blk, double *vec, DevTables tb, int wg_per_block) {
+    using g = G<D, BS>;
+    const int64_t rank = blockIdx.x / wg_per_block;
+    const int t = (blockIdx.x % wg_per_block) * blockDim.x + threadIdx.x;
+    if (t >= g::NC) return;
+    const int64_t b = tb.leaf_blk[rank];
+    if (TO_BLOCKS) blk[b * g::NC + t] = (S)vec[rank * g::NC + t];
+    else vec[rank * g::NC + t] = (double)blk[b * g::NC + t];
+}
+
+constexpr int kChunk = 4096;   // vector elements per workgroup of the inner products
+
+// partial[i * nchunk + c] = sum over chunk c of V_i[x] w[x] for i < k (V_i = V + i stride).
+__global__ void __launch_bounds__(256) k_dots(const double *V, int64_t stride, int k, const double *w, int64_t n,
+                                              double *partial, int nchunk) {
+    constexpr int PER = kChunk / 256;
+    __shared__ double red[4];
+    const int64_t x0 = (int64_t)blockIdx.x * kChunk + threadIdx.x;
+    double wr[PER];
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const int64_t x = x0 + 256 * m;
+        wr[m] = x < n ? w[x] : 0.0;
+    }
+    for (int i = 0; i < k; i++) {
+        const double *vi = V + i * stride;
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            const int64_t x = x0 + 256 * m;
+            if (x < n) s += vi[x] * wr[m];
+        }
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) partial[(int64_t)i * nchunk + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+        __syncthreads();
+    }
+}
+
+// out[i] = sum over chunks of partial[i * nchunk + c], in a fixed order.
+__global__ void __launch_bounds__(256) k_dots_reduce(const double *partial, int nchunk, double *out) {
+    __shared__ double sm[256];
+    const int i = blockIdx.x;
+    double s = 0.0;
+    for (int c = threadIdx.x; c < nchunk; c += 256) s += partial[(int64_t)i * nchunk + c];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = sm[0];
+}
+
+// y = (overwrite ? 0 : y) + sign * sum_i coef[i] V_i, coefficients in device memory.
+__global__ void __launch_bounds__(256) k_combo(double *y, const double *V, int64_t stride, const double *coef, int k,
+                                               double sign, int overwrite, int64_t n) {
+    const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (x >= n) return;
+    double s = 0.0;
+    for (int i = 0; i < k; i++) s += coef[i] * V[i * stride + x];
+    y[x] = (overwrite ? 0.0 : y[x]) + sign * s;
+}
+
+__global__ void __launch_bounds__(256) k_scale(double *x, double a, int64_t n) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q < n) x[q] *= a;
+}
 
 #define DISPATCH_DB(L, ...)                                                   \
     do {                                                                      \
@@ -1835,8 +1915,54 @@ void launch_add_leaf(const Launch &L, double *v64, double *vg64, const float *v3
     DISPATCH_DB(L, {
         constexpr int NC = G<D, BS>::NC;
         constexpr int TPB = NC < 256 ? NC : 256;
-        k_add_leaf<D, BS><<<(unsigned)(nleafblk * (NC / TPB)), TPB, 0, L.stream>>>(v64, vg64, v32, L.tb, NC / TPB);
+        k_add_leaf<D, BS, float, false><<<(unsigned)(nleafblk * (NC / TPB)), TPB, 0, L.stream>>>(v64, vg64, v32,
+                                                                                               L.tb, NC / TPB);
     });
+}
+
+void launch_add_vec(const Launch &L, double *v64, double *vg64, const double *vec, int nleafblk) {
+    if (nleafblk <= 0) return;
+    DISPATCH_DB(L, {
+        constexpr int NC = G<D, BS>::NC;
+        constexpr int TPB = NC < 256 ? NC : 256;
+        k_add_leaf<D, BS, double, true><<<(unsigned)(nleafblk * (NC / TPB)), TPB, 0, L.stream>>>(v64, vg64, vec,
+                                                                                               L.tb, NC / TPB);
+    });
+}
+
+template <typename S>
+void launch_vec_blocks(const Launch &L, S *blk, double *vec, int nleafblk, bool to_blocks) {
+    if (nleafblk <= 0) return;
+    DISPATCH_DB(L, {
+        constexpr int NC = G<D, BS>::NC;
+        constexpr int TPB = NC < 256 ? NC : 256;
+        const unsigned nb = (unsigned)(nleafblk * (NC / TPB));
+        if (to_blocks) k_vec_blocks<S, D, BS, true><<<nb, TPB, 0, L.stream>>>(blk, vec, L.tb, NC / TPB);
+        else k_vec_blocks<S, D, BS, false><<<nb, TPB, 0, L.stream>>>(blk, vec, L.tb, NC / TPB);
+    });
+}
+template void launch_vec_blocks<float>(const Launch &, float *, double *, int, bool);
+template void launch_vec_blocks<double>(const Launch &, double *, double *, int, bool);
+
+int dots_chunks(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
+
+void launch_dots(const Launch &L, const double *V, int64_t stride, int k, const double *w, int64_t n,
+                 double *partial, double *out) {
+    if (k <= 0 || n <= 0) return;
+    const int nchunk = dots_chunks(n);
+    k_dots<<<nchunk, 256, 0, L.stream>>>(V, stride, k, w, n, partial, nchunk);
+    k_dots_reduce<<<k, 256, 0, L.stream>>>(partial, nchunk, out);
+}
+
+void launch_combo(const Launch &L, double *y, const double *V, int64_t stride, const double *coef, int k, double sign,
+                  bool overwrite, int64_t n) {
+    if (n <= 0) return;
+    k_combo<<<(unsigned)((n + 255) / 256), 256, 0, L.stream>>>(y, V, stride, coef, k, sign, overwrite ? 1 : 0, n);
+}
+
+void launch_scale(const Launch &L, double *x, double a, int64_t n) {
+    if (n <= 0) return;
+    k_scale<<<(unsigned)((n + 255) / 256), 256, 0, L.stream>>>(x, a, n);
 }
 
 void launch_face_gradient(const Launch &L, const Plane<double> &P, const double *lam, const double *lamg,

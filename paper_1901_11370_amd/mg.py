@@ -47,7 +47,8 @@ class mg_params(ctypes.Structure):
     _fields_ = [("n_down", ctypes.c_int32), ("n_up", ctypes.c_int32), ("n_max_coarse", ctypes.c_int32),
                 ("coarse_abs_tol", ctypes.c_double), ("coarse_rel_tol", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("variable_eps", ctypes.c_int32),
-                ("ir_first_fmg", ctypes.c_int32), ("ir_vcycles", ctypes.c_int32), ("graphs", ctypes.c_int32)]
+                ("ir_first_fmg", ctypes.c_int32), ("ir_vcycles", ctypes.c_int32), ("graphs", ctypes.c_int32),
+                ("krylov", ctypes.c_int32)]
 
 
 mg_refine_fn = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,

@@ -76,3 +76,9 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(mg.MGError) as e:
         t.vcycle()
     assert e.value.status == mg.MG_ERR_STATE
+    # FGMRES refinement exists for the mixed form only; bounded restart length
+    with pytest.raises(mg.MGError):
+        mg.Tree([d], bs=16, bind=False, params=mg.default_params(krylov=4))
+    with pytest.raises(mg.MGError):
+        mg.Tree([d], bs=16, bind=False, params=mg.default_params(precision=mg.MG_MIXED, krylov=65))
+    mg.Tree([d], bs=16, bind=False, params=mg.default_params(precision=mg.MG_MIXED, krylov=64))
