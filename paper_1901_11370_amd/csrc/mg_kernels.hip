@@ -270,19 +270,27 @@ __device__ __forceinline__ void push_ghosts(T *__restrict__ vg, const BlockCtx<D
 // each thread then updates cells of this colour, reading f and writing v with unit
 // stride, and pushes boundary values into the mirroring ghosts.  A ghost position has
 // the colour of the cell it mirrors, so the sweep never reads what it writes.
-template <typename T, int D, int BS, bool VAR>
+// SPLIT > 1 (levels with few blocks): SPLIT workgroups share a block, each stages the
+// whole other colour and updates 1/SPLIT of the cells, which shortens every workgroup's
+// serial part.  The parts of a block are nb workgroups apart: with nb a multiple of 8
+// they run on the same XCD (workgroups go round-robin over the 8 XCDs), so the repeated
+// staging reads hit that XCD's L2.
+template <typename T, int D, int BS, bool VAR, int SPLIT>
 __global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev, int b0, int colour,
                                               uint64_t mask) {
     using g = G<D, BS>;
     constexpr int TPB = g::NH < 256 ? g::NH : 256;
     constexpr int HF = g::NF / 2;               // ghosts of one colour per face
     constexpr int NGH = 2 * D * HF;
-    constexpr int IT = g::NH / TPB;
+    constexpr int IT = g::NH / TPB / SPLIT;
+    static_assert(IT >= 1, "SPLIT too large for this block size");
     __shared__ __align__(16) T s_o[g::NH];
     __shared__ __align__(16) T s_g[NGH];
     __shared__ __align__(16) T s_eo[VAR ? g::NH : 1];
     __shared__ __align__(16) T s_eg[VAR ? NGH : 1];
-    const int64_t b = b0 + blockIdx.x;
+    const int nbl = gridDim.x / SPLIT;
+    const int64_t b = b0 + (SPLIT == 1 ? (int)blockIdx.x : (int)blockIdx.x % nbl);
+    const int q0 = SPLIT == 1 ? 0 : (blockIdx.x / nbl) * IT * TPB;   // first cell of this part
     const int oc = colour ^ 1;
     const int tid = threadIdx.x;
     // issue every load of this thread first: other colour, its ghosts, own f (and eps),
@@ -293,14 +301,14 @@ __global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev,
     st_g.load(P.vg + b * g::NG + oc * HF);
     T fr[IT], er[VAR ? IT : 1];
 #pragma unroll
-    for (int m = 0; m < IT; m++) fr[m] = P.f[b * g::NC + colour * g::NH + tid + m * TPB];
+    for (int m = 0; m < IT; m++) fr[m] = P.f[b * g::NC + colour * g::NH + q0 + tid + m * TPB];
     Stager<T, 1, VAR ? g::NH : 8, 0, TPB> st_eo;
     Stager<T, 2 * D, VAR ? HF : 8, g::NF, TPB> st_eg;
     if (VAR) {
         st_eo.load(P.eps + b * g::NC + oc * g::NH);
         st_eg.load(P.epsg + b * g::NG + oc * HF);
 #pragma unroll
-        for (int m = 0; m < IT; m++) er[m] = P.eps[b * g::NC + colour * g::NH + tid + m * TPB];
+        for (int m = 0; m < IT; m++) er[m] = P.eps[b * g::NC + colour * g::NH + q0 + tid + m * TPB];
     }
     BlockCtx<D> cx;
     cx.load(tb, b, lev);
@@ -317,7 +325,7 @@ __global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev,
     for (int a = 0; a < 3; a++) ih2[a] = a < D ? T(1.0 / (cx.h[a] * cx.h[a])) : T(0);
 #pragma unroll
     for (int m = 0; m < IT; m++) {
-        const int q = tid + m * TPB;
+        const int q = q0 + tid + m * TPB;
         const int row = q / g::RH, pos = q % g::RH;
         const int j = row % BS, k = D == 3 ? row / BS : 0;
         const int i = 2 * pos + ((j + k + colour) & 1);
@@ -622,15 +630,19 @@ __global__ void __launch_bounds__(256) k_fas(Plane<T> P, DevTables tb, int lev, 
 // One workgroup per fine block: d = v - v_old on the parent's octant and its face
 // halo is staged in LDS; the fine block is updated with unit stride and its boundary
 // values pushed into the mirroring ghosts.
-template <typename T, int D, int BS>
+// (SPLIT workgroups per block on levels with few blocks, as for the smoothing.)
+template <typename T, int D, int BS, int SPLIT>
 __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int lev, int b0, uint64_t mask,
                                                  int nt) {
     using g = G<D, BS>;
     constexpr int HB = BS / 2, HP = HB + 2;
     constexpr int NBOX = D == 3 ? HP * HP * HP : HP * HP;
     constexpr int TPB = g::NC < 256 ? g::NC : 256;
+    static_assert(SPLIT == 1 || g::NC % (TPB * SPLIT) == 0, "SPLIT must divide the block");
     __shared__ T s_d[NBOX];
-    const int64_t b = b0 + blockIdx.x;
+    const int nbl = gridDim.x / SPLIT;   // parts of a block nb workgroups apart (same XCD)
+    const int64_t b = b0 + (SPLIT == 1 ? (int)blockIdx.x : (int)blockIdx.x % nbl);
+    const int t0 = SPLIT == 1 ? 0 : (blockIdx.x / nbl) * (g::NC / SPLIT);
     const int tid = threadIdx.x;
     // the block's tables, all independent loads; the octant of the block in its parent
     // follows from its own origin (block coordinates' parity)
@@ -642,13 +654,13 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
     int po[3] = {0, 0, 0};
     for (int a = 0; a < D; a++) po[a] = ((gc0[a] / HB) & 1) * HB;
     constexpr int ITB = (NBOX + TPB - 1) / TPB;
-    constexpr int IT = (g::NC + TPB - 1) / TPB;
+    constexpr int IT = (g::NC / SPLIT + TPB - 1) / TPB;
     const TailGeo tg = tail_geo(tb, dm, nt - 1, D);
     // issue all loads first: the fine values this thread updates, then the staged box
     T vr[IT];
 #pragma unroll
     for (int m = 0; m < IT; m++) {
-        const int t = tid + m * TPB;
+        const int t = t0 + tid + m * TPB;
         vr[m] = P.v[b * g::NC + (g::NC % TPB == 0 || t < g::NC ? t : 0)];
     }
     // box cell -> addresses of v and v_old (edges and corners of the halo, never
@@ -687,7 +699,7 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
     if (!((mask >> dm) & 1)) return;
 #pragma unroll
     for (int m = 0; m < IT; m++) {
-        const int t = tid + m * TPB;
+        const int t = t0 + tid + m * TPB;
         if (g::NC % TPB != 0 && t >= g::NC) break;
         int i, j, k;
         g::decode(t, i, j, k);
@@ -1700,16 +1712,20 @@ void K<T>::gsrb(const Launch &L, const Plane<T> &P, int lev, int b0, int nb, int
     DISPATCH_DB(L, {
         constexpr int NH = G<D, BS>::NH;
         constexpr int TPB = NH < 256 ? NH : 256;
+        constexpr int SP = NH / TPB >= 4 ? 4 : 1;
         if (ev0) {
             if (var)
-                hipExtLaunchKernelGGL((k_gsrb<T, D, BS, true>), dim3(nb), dim3(TPB), 0, L.stream, ev0, ev1, 0, P, L.tb,
-                                      lev, b0, colour, mask);
+                hipExtLaunchKernelGGL((k_gsrb<T, D, BS, true, 1>), dim3(nb), dim3(TPB), 0, L.stream, ev0, ev1, 0, P,
+                                      L.tb, lev, b0, colour, mask);
             else
-                hipExtLaunchKernelGGL((k_gsrb<T, D, BS, false>), dim3(nb), dim3(TPB), 0, L.stream, ev0, ev1, 0, P, L.tb,
-                                      lev, b0, colour, mask);
+                hipExtLaunchKernelGGL((k_gsrb<T, D, BS, false, 1>), dim3(nb), dim3(TPB), 0, L.stream, ev0, ev1, 0, P,
+                                      L.tb, lev, b0, colour, mask);
+        } else if (SP > 1 && nb <= 256) {
+            if (var) k_gsrb<T, D, BS, true, SP><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+            else k_gsrb<T, D, BS, false, SP><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
         } else {
-            if (var) k_gsrb<T, D, BS, true><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
-            else k_gsrb<T, D, BS, false><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+            if (var) k_gsrb<T, D, BS, true, 1><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+            else k_gsrb<T, D, BS, false, 1><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
         }
     });
 }
@@ -1764,7 +1780,9 @@ void K<T>::correct(const Launch &L, const Plane<T> &P, int lev, int b0, int nb, 
     DISPATCH_DB(L, {
         constexpr int NC = G<D, BS>::NC;
         constexpr int TPB = NC < 256 ? NC : 256;
-        k_correct<T, D, BS><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, L.nt);
+        constexpr int SP = NC / TPB >= 4 ? 4 : 1;
+        if (SP > 1 && nb <= 256) k_correct<T, D, BS, SP><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, L.nt);
+        else k_correct<T, D, BS, 1><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, L.nt);
     });
 }
 
