@@ -39,7 +39,8 @@ def _args():
     p.add_argument("--no-mixed", action="store_true")
     p.add_argument("--cpu-sample-cycles", type=int, default=1, help="V-cycles after the FMG in the CPU sample")
     p.add_argument("--workload", default="periodic256",
-                   choices=["periodic256", "dirichlet2d", "amr-literal", "amr-nested", "varcoef-nested", "batch"],
+                   choices=["periodic256", "dirichlet2d", "amr-literal", "amr-nested", "varcoef-nested", "batch",
+                            "tree-build"],
                    help="periodic256 is the benchmark line; the others print report lines")
     p.add_argument("--max-cycles", type=int, default=60)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -222,6 +223,38 @@ def report(a):
         out["value"] = out["fp64"]["value"]
         out["ms_per_step"] = out["fp64"]["time_to_tol_ms"]
         out["dtype"] = "f64"
+        print(json.dumps(out), flush=True)
+        return
+    if a.workload == "tree-build":
+        # step a1: host construction of the tree and tables (the paper quotes ~0.3 s for
+        # a uniform 1024^3 grid of 16^3 blocks), then binding (table upload, field init)
+        out = dict(base, metric="tree build time", unit="s", higher_is_better=False, dtype="-",
+                   config={"workload": "uniform 1024^3 in 16^3 blocks, and the nested AMR tree"})
+        d = mg.Domain(3, [1024] * 3, [0, 0, 0], [1, 1, 1], [mg.MG_BC_DIRICHLET] * 6)
+        times = []
+        for _ in range(max(a.steps, 1)):
+            t0 = time.perf_counter()
+            t = mg.Tree([d], bs=16, bind=False)
+            times.append(time.perf_counter() - t0)
+            del t
+        out["create_s_1024"] = sorted(times)[len(times) // 2]
+        t = mg.Tree([d], bs=16, bind=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t.bind()                      # store allocation, table upload, field initialisation
+        torch.cuda.synchronize()
+        out["bind_s_1024"] = time.perf_counter() - t0
+        out["store_gb_1024"] = t.storage_bytes / 1e9
+        del t
+        torch.cuda.empty_cache()
+        w = W.config3(nested=True)
+        dd = w.domains[0]
+        t0 = time.perf_counter()
+        t = mg.Tree([mg.Domain(dd.dim, dd.base_cells, dd.lo, dd.hi, dd.bc_kind)], bs=16, max_refine=w.max_refine,
+                    refine=w.refine, bind=False)
+        out["create_s_nested_amr"] = time.perf_counter() - t0
+        out["value"] = out["create_s_1024"]
+        out["ms_per_step"] = out["create_s_1024"] * 1e3
         print(json.dumps(out), flush=True)
         return
     if a.workload == "batch":

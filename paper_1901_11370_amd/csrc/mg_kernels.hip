@@ -769,7 +769,7 @@ __device__ __forceinline__ int tix(const TailLev &g, int i, int j, int k) {
 template <typename T, int D, bool VAR>
 struct Tail {
     const TailLev *lv;         // [levels] in LDS
-    const TailBC *bc;          // in LDS
+    TailBC bc;                 // boundary data (registers)
     double *red;               // reduction scratch in LDS, one slot per wave
     T *tv, *tvold, *tf, *teps; // this domain's tail arrays (LDS or global memory)
     T *tvold_top;              // with the arrays in LDS: v_old of the top grid, in global
@@ -802,7 +802,7 @@ struct Tail {
             for (int side = 0; side < 2; side++) {
                 if (c[a] != (side ? g.n[a] - 1 : 0)) continue;
                 const int f = 2 * a + side;
-                const int kind = bc->kind[f];
+                const int kind = bc.kind[f];
                 int q[3] = {i, j, k};
                 T val;
                 if (kind == MG_BC_PERIODIC) {
@@ -811,7 +811,7 @@ struct Tail {
                     val = nv;
                 } else {
                     q[a] = side ? g.n[a] : -1;
-                    val = bc_ghost<T>(kind, bc->value[f], g.h[a], side, nv);
+                    val = bc_ghost<T>(kind, bc.value[f], g.h[a], side, nv);
                 }
                 u[tix<D>(g, q[0], q[1], q[2])] = val;
             }
@@ -820,7 +820,7 @@ struct Tail {
     // The whole ghost layer of one grid (faces only): periodic copy or boundary
     // condition (for eps, a copy of the interior cell).
     __device__ __forceinline__ void fill_ghosts(int lev, T *u, bool eps) const {
-        const TailLev &g = lv[lev];
+        const TailLev g = lv[lev];
 #pragma unroll
         for (int a = 0; a < D; a++) {
             const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
@@ -838,12 +838,13 @@ struct Tail {
                 in[a] = side ? g.n[a] - 1 : 0;
                 op[a] = side ? 0 : g.n[a] - 1;
                 if (D == 2) c[2] = in[2] = op[2] = 0;
-                const int f = 2 * a + side;
-                const int kind = bc->kind[f];
+                // selects, not a run-time index into bc (which would live in scratch)
+                const int kind = side ? bc.kind[2 * a + 1] : bc.kind[2 * a];
+                const double bval = side ? bc.value[2 * a + 1] : bc.value[2 * a];
                 T val;
                 if (kind == MG_BC_PERIODIC) val = u[tix<D>(g, op[0], op[1], op[2])];
                 else if (eps) val = u[tix<D>(g, in[0], in[1], in[2])];
-                else val = bc_ghost<T>(kind, bc->value[f], g.h[a], side, u[tix<D>(g, in[0], in[1], in[2])]);
+                else val = bc_ghost<T>(kind, bval, g.h[a], side, u[tix<D>(g, in[0], in[1], in[2])]);
                 u[tix<D>(g, c[0], c[1], c[2])] = val;
             }
         }
@@ -872,7 +873,7 @@ struct Tail {
 
     // One colour of Gauss-Seidel on grid lev, then a barrier.
     __device__ __forceinline__ void sweep(int lev, int colour) const {
-        const TailLev &g = lv[lev];
+        const TailLev g = lv[lev];
         const bool gp = g.ghost_pass;
         const int ns = nslot(g);
         for (int s = threadIdx.x; s < ns; s += blockDim.x) {
@@ -928,7 +929,7 @@ struct Tail {
     }
 
     __device__ __forceinline__ double resmax(int lev) const {
-        const TailLev &g = lv[lev];
+        const TailLev g = lv[lev];
         double m = 0.0;
         for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
             int i, j, k;
@@ -941,7 +942,7 @@ struct Tail {
 
     // v_old = v (ghosts included) and f += L v on grid lev (ghosts already valid).
     __device__ __forceinline__ void fas(int lev) const {
-        const TailLev &g = lv[lev];
+        const TailLev g = lv[lev];
         if (tvold_top && lev == top) {
             for (int q = threadIdx.x; q < g.npad; q += blockDim.x) tvold_top[g.off + q] = tv[g.off + q];
         } else {
@@ -963,7 +964,7 @@ struct Tail {
     // Restriction lev -> lev-1 of v and of the residual (pushing the coarse ghosts),
     // then the FAS right-hand side there.
     __device__ __forceinline__ void restrict_fas(int lev) const {
-        const TailLev &gf = lv[lev], &gc = lv[lev - 1];
+        const TailLev gf = lv[lev], gc = lv[lev - 1];
         for (int c = threadIdx.x; c < gc.ncell; c += blockDim.x) {
             int I, J, K;
             cell(gc, c, I, J, K);
@@ -987,7 +988,7 @@ struct Tail {
     // Prolongation of v - v_old from lev-1 (eq. interp_2d / interp_3d) added to lev,
     // with the ghosts of lev pushed.
     __device__ __forceinline__ void correct(int lev) const {
-        const TailLev &gf = lv[lev], &gc = lv[lev - 1];
+        const TailLev gf = lv[lev], gc = lv[lev - 1];
         for (int c = threadIdx.x; c < gf.ncell; c += blockDim.x) {
             int i, j, k;
             cell(gf, c, i, j, k);
@@ -1014,9 +1015,9 @@ struct Tail {
     // alternation of a one-cell Dirichlet grid).  Fully periodic: remove the mean of
     // f first.
     __device__ __forceinline__ int coarse_solve(const TailParams &tp) const {
-        const TailLev &g = lv[0];
+        const TailLev g = lv[0];
         bool per = true;
-        for (int f = 0; f < 2 * D; f++) per = per && bc->kind[f] == MG_BC_PERIODIC;
+        for (int f = 0; f < 2 * D; f++) per = per && bc.kind[f] == MG_BC_PERIODIC;
         if (per) {
             double s = 0.0;
             for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
@@ -1189,12 +1190,12 @@ __global__ void __launch_bounds__(VAR ? 512 : 1024) k_tail(Plane<T> P, DevTables
         if (VAR)
             for (int q = threadIdx.x; q < n; q += blockDim.x) se[q] = P.teps[first + q];
         __syncthreads();
-        const Tail<T, D, VAR> tl{lvs, &bcs, red, sv, so, sf, VAR ? se : nullptr, P.tvold + first, top};
+        const Tail<T, D, VAR> tl{lvs, bcs, red, sv, so, sf, VAR ? se : nullptr, P.tvold + first, top};
         steps = tl.run(ops, nops, tp);
         for (int q = threadIdx.x; q < g.npad; q += blockDim.x) P.tv[first + g.off + q] = sv[g.off + q];
     } else {
         __syncthreads();
-        const Tail<T, D, VAR> tl{lvs, &bcs, red, P.tv + first, P.tvold + first, P.tf + first,
+        const Tail<T, D, VAR> tl{lvs, bcs, red, P.tv + first, P.tvold + first, P.tf + first,
                                  VAR ? P.teps + first : nullptr, nullptr, top};
         steps = tl.run(ops, nops, tp);
     }
@@ -1212,7 +1213,7 @@ __global__ void __launch_bounds__(512) k_tail_eps(Plane<T> P, DevTables tb, int 
     tail_span(tb, dm, nt - 1, D, &first);
     tail_setup(tb, dm, nt, D, first, lvs, &bcs);
     __syncthreads();
-    const Tail<T, D, true> tl{lvs, &bcs, red, P.tv + first, P.tvold + first, P.tf + first, P.teps + first,
+    const Tail<T, D, true> tl{lvs, bcs, red, P.tv + first, P.tvold + first, P.tf + first, P.teps + first,
                               nullptr, nt - 1};
     for (int l = nt - 1; l >= 1; l--) {
         const TailLev &gf = lvs[l], &gc = lvs[l - 1];

@@ -165,6 +165,16 @@ std::string build_tree(HostTree &T, const mg_domain *doms, int ndom, int bs, int
 
     Builder bld;
     bld.dim = dim; bld.bs = bs; bld.nt = nt; bld.doms = &T.doms;
+    {
+        size_t est = 0;   // blocks of the levels up to the base grids
+        for (const HDomain &hd : T.doms) {
+            size_t per = 1;
+            for (int a = 0; a < dim; a++) per *= (size_t)hd.nblk_low[a];
+            for (int l = nt; l <= hd.base; l++) est += per << (dim * (l - nt));
+        }
+        bld.at.reserve(est + est / 2);
+        bld.B.reserve(est + est / 2);
+    }
     // Every block of the levels up to the base grid exists.
     for (int i = 0; i < ndom; i++) {
         for (int l = nt; l <= T.doms[i].base; l++) {
@@ -221,11 +231,11 @@ std::string build_tree(HostTree &T, const mg_domain *doms, int ndom, int bs, int
     std::vector<int> newid(bld.B.size(), -1);
     std::vector<std::vector<std::vector<int>>> groups(T.nlev, std::vector<std::vector<int>>(ndom));
     for (int id = 0; id < (int)bld.B.size(); id++) groups[bld.B[id].lev][bld.B[id].dom].push_back(id);
+    std::vector<uint64_t> mcode(bld.B.size());
+    for (size_t id = 0; id < bld.B.size(); id++) mcode[id] = morton_code(bld.B[id].bc, dim);
     for (int l = 0; l < T.nlev; l++)
         for (int i = 0; i < ndom; i++)
-            std::sort(groups[l][i].begin(), groups[l][i].end(), [&](int a, int b) {
-                return morton_code(bld.B[a].bc, dim) < morton_code(bld.B[b].bc, dim);
-            });
+            std::sort(groups[l][i].begin(), groups[l][i].end(), [&](int a, int b) { return mcode[a] < mcode[b]; });
     T.lev_first.assign(T.nlev + 1, 0);
     int next = 0;
     for (int l = 0; l < T.nlev; l++) {

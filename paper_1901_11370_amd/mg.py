@@ -180,7 +180,7 @@ class Tree:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and mg_tree_destroy is not None:   # None during interpreter shutdown
             mg_tree_destroy(h)
             self.h = None
 
