@@ -72,6 +72,8 @@ def lib():
         L.og_fill_ghosts_level.argtypes = [vp, ctypes.c_int]
         L.og_restrict_all.argtypes = [vp]
         L.og_correct_level.argtypes = [vp, ctypes.c_int]
+        L.og_smooth_level.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+        L.og_set_smoother.argtypes = [vp, ctypes.c_int, d]
         _lib = L
     return _lib
 
@@ -127,6 +129,11 @@ class OracleTree:
     # structure
     def set_params(self, n_down=2, n_up=2, n_max=1000, abs_tol=0.0, rel_tol=1e-8):
         lib().og_set_params(self._h, n_down, n_up, n_max, abs_tol, rel_tol)
+
+    GSRB, JACOBI = 0, 1
+
+    def set_smoother(self, kind, omega=2.0 / 3.0):
+        lib().og_set_smoother(self._h, kind, omega)
 
     @property
     def num_levels(self):
@@ -252,3 +259,6 @@ class OracleTree:
 
     def correct_level(self, l):
         lib().og_correct_level(self._h, l)
+
+    def smooth_level(self, l, n=1):
+        lib().og_smooth_level(self._h, l, n)

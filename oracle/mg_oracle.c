@@ -51,6 +51,8 @@ struct og_tree {
     int nblk, cap;
     int n_down, n_up, n_max;
     double abs_tol, rel_tol;
+    int smoother;    /* OG_SMOOTH_GSRB or OG_SMOOTH_JACOBI */
+    double omega;    /* Jacobi weight */
     int *leaf;       /* leaf blocks in canonical order */
     int nleaf;
     int last_coarse_steps;
@@ -231,6 +233,7 @@ og_tree *og_create(int dim, const int32_t *base_cells, const double *lo, const d
         t->hi[d] = d < dim ? hi[d] : 1.0;
     }
     t->n_down = 2; t->n_up = 2; t->n_max = 1000; t->abs_tol = 0.0; t->rel_tol = 1e-8;
+    t->smoother = OG_SMOOTH_GSRB; t->omega = 2.0 / 3.0;
     t->refine = refine; t->ud = ud;
 
     /* Added coarse grids (Sec. 2.5): halve the grid while every halved size still
@@ -354,6 +357,11 @@ void og_destroy(og_tree *t) {
 void og_set_params(og_tree *t, int n_down, int n_up, int n_max, double abs_tol, double rel_tol) {
     t->n_down = n_down; t->n_up = n_up; t->n_max = n_max;
     t->abs_tol = abs_tol; t->rel_tol = rel_tol;
+}
+
+void og_set_smoother(og_tree *t, int kind, double omega) {
+    t->smoother = kind;
+    t->omega = omega;
 }
 
 int og_num_levels(const og_tree *t) { return t->nlev; }
@@ -555,8 +563,36 @@ static double gs_value(const og_tree *t, int l, const OBlock *B, int i, int j, i
  * indices, then the odd ones.  Ghost cells are refreshed after each colour, so a
  * blocked sweep equals a sweep over the whole level (Sec. 2.6 states that ghosts are
  * updated after, not during, a smoothing step). */
+/* Weighted Jacobi (the smoother of the paper's timing runs, Sec. 3.3; the weight is not
+ * given there): every cell moves the fraction omega of the way from its value to its
+ * Gauss-Seidel local solution, all computed from the values before the step (held in
+ * the residual field meanwhile); then ghosts are refreshed. */
+static void jacobi_step(og_tree *t, int l) {
+    const OLevel *L = &t->lev[l];
+    for (int q = 0; q < L->n; q++) {
+        OBlock *B = &t->blk[L->list[q]];
+        FOR_CELLS(t, l, i, j, k) {
+            int p = pidx(t, l, i, j, k);
+            double v = B->fld[F_V][p];
+            B->fld[F_R][p] = v + t->omega * (gs_value(t, l, B, i, j, k) - v);
+        }
+    }
+    for (int q = 0; q < L->n; q++) {
+        OBlock *B = &t->blk[L->list[q]];
+        FOR_CELLS(t, l, i, j, k) {
+            int p = pidx(t, l, i, j, k);
+            B->fld[F_V][p] = B->fld[F_R][p];
+        }
+    }
+    og_fill_ghosts_level(t, l);
+}
+
 static void smooth_step(og_tree *t, int l) {
     const OLevel *L = &t->lev[l];
+    if (t->smoother == OG_SMOOTH_JACOBI) {
+        jacobi_step(t, l);
+        return;
+    }
     for (int colour = 0; colour < 2; colour++) {
         for (int q = 0; q < L->n; q++) {
             OBlock *B = &t->blk[L->list[q]];
@@ -659,6 +695,10 @@ static void correct_level(og_tree *t, int l) {
         }
     }
     og_fill_ghosts_level(t, l);
+}
+
+void og_smooth_level(og_tree *t, int l, int n) {
+    for (int s = 0; s < n; s++) smooth_step(t, l);
 }
 
 void og_correct_level(og_tree *t, int l) { correct_level(t, l); }

@@ -40,6 +40,9 @@ og_tree *og_create(int dim, const int32_t *base_cells, const double *lo, const d
 void og_destroy(og_tree *t);
 
 void og_set_params(og_tree *t, int n_down, int n_up, int n_max, double abs_tol, double rel_tol);
+/* Smoother: red-black Gauss-Seidel (default) or weighted Jacobi with weight omega. */
+enum { OG_SMOOTH_GSRB = 0, OG_SMOOTH_JACOBI = 1 };
+void og_set_smoother(og_tree *t, int kind, double omega);
 
 /* Structure queries. */
 int og_num_levels(const og_tree *t);
@@ -86,6 +89,8 @@ void og_fill_ghosts_level(og_tree *t, int l);
 void og_restrict_all(og_tree *t);
 /* v^h += P(v^H - v_old^H) on level l, then ghosts of level l. */
 void og_correct_level(og_tree *t, int l);
+/* n smoothing steps on level l (ghosts of the level must be current). */
+void og_smooth_level(og_tree *t, int l, int n);
 
 #ifdef __cplusplus
 }
