@@ -76,6 +76,7 @@ typedef int (*mg_refine_fn)(void *user_data, int domain, int level, const int32_
                             int bs);
 
 enum { MG_FP64 = 0, MG_MIXED = 1 };
+enum { MG_SMOOTH_GSRB = 0, MG_SMOOTH_JACOBI = 1 };
 
 typedef struct {
     int32_t n_down;           /* smoothing steps before restriction (paper default 2) */
@@ -97,6 +98,12 @@ typedef struct {
                                  and update per restart; needs (2m + 1) FP64 leaf vectors in
                                  the store.  For coefficients with large jumps, where the
                                  plain cycles stall.  At most 64. */
+    int32_t smoother;         /* MG_SMOOTH_GSRB (default; Sec. 2.2 red-black Gauss-Seidel)
+                                 or MG_SMOOTH_JACOBI (weighted Jacobi, the smoother of the
+                                 paper's timing runs, Sec. 3.3); one Jacobi step counts as
+                                 one smoothing step */
+    double jacobi_weight;     /* Jacobi weight in (0, 1]; default 2/3 (not given in the
+                                 paper) */
 } mg_params;
 
 /* Fills p with the paper's defaults (Sec. 2.4) and FP64 precision. */

@@ -99,6 +99,7 @@ struct Layout {
 };
 
 bool mixed(const mg_tree *t) { return t->prm.precision == MG_MIXED; }
+bool jacobi(const mg_tree *t) { return t->prm.smoother == MG_SMOOTH_JACOBI; }
 bool var(const mg_tree *t) { return t->prm.variable_eps != 0; }
 
 // Computes the byte offsets of every array of the store; with base != nullptr also
@@ -194,6 +195,8 @@ size_t plan(mg_tree *t, char *base) {
         if (var(t)) { oe = L.take<TT>(nb * nc); oeg = L.take<TT>(nb * ng); }
         size_t otv = L.take<TT>(T.tail_cells), oto = L.take<TT>(T.tail_cells), otf = L.take<TT>(T.tail_cells);
         size_t ote = var(t) ? L.take<TT>(T.tail_cells) : 0;
+        size_t ov2 = 0, ovg2 = 0, otv2 = 0;
+        if (jacobi(t)) { ov2 = L.take<TT>(nb * nc); ovg2 = L.take<TT>(nb * ng); otv2 = L.take<TT>(T.tail_cells); }
         if (base) {
             pl->v = (TT *)P(ov); pl->vg = (TT *)P(ovg);
             pl->vold = (TT *)P(oo); pl->voldg = (TT *)P(oog);
@@ -202,6 +205,9 @@ size_t plan(mg_tree *t, char *base) {
             pl->epsg = var(t) ? (TT *)P(oeg) : nullptr;
             pl->tv = (TT *)P(otv); pl->tvold = (TT *)P(oto); pl->tf = (TT *)P(otf);
             pl->teps = var(t) ? (TT *)P(ote) : nullptr;
+            pl->v2 = jacobi(t) ? (TT *)P(ov2) : nullptr;
+            pl->vg2 = jacobi(t) ? (TT *)P(ovg2) : nullptr;
+            pl->tv2 = jacobi(t) ? (TT *)P(otv2) : nullptr;
         }
     };
     plane(&t->P64, double(0));
@@ -261,6 +267,8 @@ TailParams tail_params(const mg_tree *t) {
     TailParams tp;
     tp.n_down = t->prm.n_down; tp.n_up = t->prm.n_up; tp.n_max = t->prm.n_max_coarse;
     tp.abs_tol = t->prm.coarse_abs_tol; tp.rel_tol = t->prm.coarse_rel_tol;
+    tp.jacobi = jacobi(t) ? 1 : 0;
+    tp.omega = t->prm.jacobi_weight;
     return tp;
 }
 
@@ -277,7 +285,38 @@ struct Driver {
 
     void ghost_level(int l, uint64_t m) { K<T>::ghost(L, P, lvb0(t, l), lvnb(t, l), nullptr, 0, m, false, false); }
 
+    // Weighted Jacobi: steps alternate between v and its second copy; after an odd
+    // number the level's blocks are copied back.  Coarse-fine ghosts of the copy being
+    // written take their coarse values from v of the coarser level.
+    void jacobi_smooth(int l, uint64_t m, int steps) {
+        const int ncf = (int)t->T.cf_of_level[l].size();
+        const int b0 = lvb0(t, l), nb = lvnb(t, l);
+        for (int s = 0; s < steps; s++) {
+            const bool fwd = (s & 1) == 0;
+            Plane<T> S = P;
+            if (!fwd) { S.v = P.v2; S.vg = P.vg2; }
+            T *dst = fwd ? P.v2 : P.v, *dstg = fwd ? P.vg2 : P.vg;
+            K<T>::jacobi(L, S, dst, dstg, l, b0, nb, m, v, t->prm.jacobi_weight);
+            if (ncf) {
+                Plane<T> Dp = P;
+                Dp.v = dst;
+                Dp.vg = dstg;
+                Dp.vc = P.v;
+                Dp.vcg = P.vg;
+                K<T>::ghost(L, Dp, 0, 0, t->d_cfs[l], ncf, m, false, true);
+            }
+        }
+        if (steps & 1) {
+            K<T>::copy(L, P.v + (size_t)b0 * t->nc, P.v2 + (size_t)b0 * t->nc, (size_t)nb * t->nc);
+            K<T>::copy(L, P.vg + (size_t)b0 * t->ng, P.vg2 + (size_t)b0 * t->ng, (size_t)nb * t->ng);
+        }
+    }
+
     void smooth(int l, uint64_t m, int steps) {
+        if (jacobi(t)) {
+            jacobi_smooth(l, m, steps);
+            return;
+        }
         const bool timed = t->prof && l == t->T.nlev - 1;
         const int ncf = (int)t->T.cf_of_level[l].size();
         for (int s = 0; s < steps; s++)
@@ -342,6 +381,17 @@ struct Driver {
     }
     void usmooth(int dm, int l, int steps) {
         const UGrid g = ugrid(dm, l);
+        if (jacobi(t)) {
+            for (int s = 0; s < steps; s++) {
+                const bool fwd = (s & 1) == 0;
+                K<T>::ujacobi(L, P, fwd ? P.tv : P.tv2, fwd ? P.tv2 : P.tv, g, v, t->prm.jacobi_weight);
+            }
+            if (steps & 1) {
+                size_t npad = (size_t)(g.n[0] + 2) * (g.n[1] + 2) * (t->T.dim == 3 ? g.n[2] + 2 : 1);
+                K<T>::copy(L, P.tv + g.off, P.tv2 + g.off, npad);
+            }
+            return;
+        }
         for (int s = 0; s < steps; s++)
             for (int c = 0; c < 2; c++) K<T>::ugsrb(L, P, g, c, v);
     }
@@ -701,6 +751,8 @@ int mg_default_params(mg_params *p) {
     p->ir_vcycles = 1;
     p->graphs = 1;
     p->krylov = 0;
+    p->smoother = MG_SMOOTH_GSRB;
+    p->jacobi_weight = 2.0 / 3.0;
     return MG_OK;
 }
 
@@ -714,7 +766,9 @@ int mg_tree_create(const mg_domain *domains, int n_domains, int block_size, int 
     const mg_params &p = t->prm;
     if (p.n_down < 0 || p.n_up < 0 || p.n_max_coarse < 1 || p.coarse_rel_tol < 0 || p.coarse_abs_tol < 0 ||
         (p.precision != MG_FP64 && p.precision != MG_MIXED) || p.ir_vcycles < 1 || (p.graphs != 0 && p.graphs != 1) ||
-        p.krylov < 0 || p.krylov > 64 || (p.krylov > 0 && p.precision != MG_MIXED)) {
+        p.krylov < 0 || p.krylov > 64 || (p.krylov > 0 && p.precision != MG_MIXED) ||
+        (p.smoother != MG_SMOOTH_GSRB && p.smoother != MG_SMOOTH_JACOBI) ||
+        !(p.jacobi_weight > 0.0 && p.jacobi_weight <= 1.0)) {
         delete t;
         return MG_ERR_ARG;
     }

@@ -58,11 +58,15 @@ template <typename T>
 struct Plane {
     T *v, *vg, *vold, *voldg, *f, *eps, *epsg;
     T *tv, *tvold, *tf, *teps;
+    T *v2, *vg2, *tv2;   // second copies of v for the Jacobi smoother (else null)
+    const T *vc, *vcg;   // if set: v of the coarser level for coarse-fine ghosts (else v)
 };
 
 struct TailParams {
     int n_down, n_up, n_max;
     double abs_tol, rel_tol;
+    int jacobi;          // 0: red-black Gauss-Seidel, 1: weighted Jacobi
+    double omega;        // Jacobi weight
 };
 
 // Launch context.
@@ -102,6 +106,13 @@ struct K {
     static void ufas(const Launch &L, const Plane<T> &P, const UGrid &g, bool var);
     static void urestrict(const Launch &L, const Plane<T> &P, const UGrid &g, const UGrid &gc, bool var);
     static void ucorrect(const Launch &L, const Plane<T> &P, const UGrid &g, const UGrid &gc);
+    // Weighted Jacobi step on one level's blocks: reads v (P.v, P.vg), writes dst, dstg.
+    static void jacobi(const Launch &L, const Plane<T> &P, T *dst, T *dstg, int lev, int b0, int nb, uint64_t mask,
+                       bool var, double omega);
+    // Weighted Jacobi step on a large coarse grid: src -> dst (tail arrays).
+    static void ujacobi(const Launch &L, const Plane<T> &P, const T *src, T *dst, const UGrid &g, bool var,
+                        double omega);
+    static void copy(const Launch &L, T *dst, const T *src, size_t n);
     static void gather(const Launch &L, const T *src, double *dst, int nleafblk);
 };
 

@@ -363,6 +363,85 @@ __global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev,
     }
 }
 
+// ------------------------------------------------------ weighted Jacobi step
+// Every cell of the level's blocks moves the fraction omega of the way to its
+// Gauss-Seidel local solution computed from the values before the step (the smoother of
+// the paper's timing runs, Sec. 3.3).  Reads v (P.v, P.vg), writes dst and pushes the
+// mirroring ghosts into dstg; one workgroup per block, the block and its ghosts staged
+// in LDS.
+template <typename T, int D, int BS, bool VAR>
+__global__ void __launch_bounds__(256) k_jacobi(Plane<T> P, T *__restrict__ dst, T *__restrict__ dstg, DevTables tb,
+                                                int lev, int b0, uint64_t mask, double omega) {
+    using g = G<D, BS>;
+    constexpr int TPB = g::NC < 256 ? g::NC : 256;
+    constexpr int IT = g::NC / TPB;
+    __shared__ __align__(16) T s_v[g::NC + g::NG];
+    const int64_t b = b0 + blockIdx.x;
+    const int tid = threadIdx.x;
+    Stager<T, 1, g::NC, 0, TPB> st_v;
+    Stager<T, 1, g::NG, 0, TPB> st_g;
+    st_v.load(P.v + b * g::NC);
+    st_g.load(P.vg + b * g::NG);
+    T fr[IT];
+#pragma unroll
+    for (int m = 0; m < IT; m++) fr[m] = P.f[b * g::NC + tid + m * TPB];
+    BlockCtx<D> cx;
+    cx.load(tb, b, lev);
+    st_v.store(s_v);
+    st_g.store(s_v + g::NC);
+    __syncthreads();
+    if (!((mask >> cx.dm) & 1)) return;
+    T ih2[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) ih2[a] = a < D ? T(1.0 / (cx.h[a] * cx.h[a])) : T(0);
+    const T om = T(omega);
+#pragma unroll
+    for (int m = 0; m < IT; m++) {
+        const int t = tid + m * TPB;
+        int i, j, k;
+        g::decode(t, i, j, k);
+        const T vc = s_v[t];
+        T nb[6];
+        nb[0] = i > 0 ? s_v[g::in(i - 1, j, k)] : s_v[g::NC + g::gh(0, j, k)];
+        nb[1] = i < BS - 1 ? s_v[g::in(i + 1, j, k)] : s_v[g::NC + g::gh(1, j, k)];
+        nb[2] = j > 0 ? s_v[g::in(i, j - 1, k)] : s_v[g::NC + g::gh(2, i, k)];
+        nb[3] = j < BS - 1 ? s_v[g::in(i, j + 1, k)] : s_v[g::NC + g::gh(3, i, k)];
+        if (D == 3) {
+            nb[4] = k > 0 ? s_v[g::in(i, j, k - 1)] : s_v[g::NC + g::gh(4, i, j)];
+            nb[5] = k < BS - 1 ? s_v[g::in(i, j, k + 1)] : s_v[g::NC + g::gh(5, i, j)];
+        }
+        T num = T(0), den = T(0);
+        if (!VAR) {
+#pragma unroll
+            for (int f = 0; f < 2 * D; f++) {
+                num += ih2[f >> 1] * nb[f];
+                den += ih2[f >> 1];
+            }
+        } else {
+            const T e0 = P.eps[b * g::NC + t];
+            T en[6];
+            en[0] = ld<D, BS>(P.eps, P.epsg, b, i - 1, j, k);
+            en[1] = ld<D, BS>(P.eps, P.epsg, b, i + 1, j, k);
+            en[2] = ld<D, BS>(P.eps, P.epsg, b, i, j - 1, k);
+            en[3] = ld<D, BS>(P.eps, P.epsg, b, i, j + 1, k);
+            if (D == 3) {
+                en[4] = ld<D, BS>(P.eps, P.epsg, b, i, j, k - 1);
+                en[5] = ld<D, BS>(P.eps, P.epsg, b, i, j, k + 1);
+            }
+#pragma unroll
+            for (int f = 0; f < 2 * D; f++) {
+                const T w = harm(e0, en[f]) * ih2[f >> 1];
+                num += w * nb[f];
+                den += w;
+            }
+        }
+        const T gs = (num - fr[m]) / den;
+        const T nv = vc + om * (gs - vc);
+        dst[b * g::NC + t] = nv;
+        push_ghosts<T, D, BS>(dstg, cx, b, i, j, k, nv);
+    }
+}
+
 // -------------------------------------------------------------- ghost fill
 // Fills the face ghosts of a block (Sec. 2.6).  Same-level faces copy the
 // neighbour's boundary cell; physical faces apply the boundary condition; coarse-fine
@@ -413,8 +492,8 @@ __device__ void ghost_cell(const Plane<T> &P, const DevTables &tb, int64_t b, in
         int cl[3];
         for (int c = 0; c < 3; c++) cl[c] = (gi[c] >> 1) - tb.org[3 * qb + c];
         if (D == 2) cl[2] = 0;
-        const T *w = EPS ? P.eps : P.v;
-        const T *wg = EPS ? P.epsg : P.vg;
+        const T *w = EPS ? P.eps : (P.vc ? P.vc : P.v);
+        const T *wg = EPS ? P.epsg : (P.vcg ? P.vcg : P.vg);
         T B = w[qb * g::NC + g::in(cl[0], cl[1], cl[2])];
         if (EPS) {
             out = B;
@@ -774,6 +853,9 @@ struct Tail {
     T *tv, *tvold, *tf, *teps; // this domain's tail arrays (LDS or global memory)
     T *tvold_top;              // with the arrays in LDS: v_old of the top grid, in global
     int top;                   // memory (only the block level above reads it)
+    T *ttmp;                   // Jacobi: global scratch grids (same offsets) for large grids
+    int jac;                   // smoother: 0 red-black Gauss-Seidel, 1 weighted Jacobi
+    double omega;              // Jacobi weight
 
     __device__ __forceinline__ void cell(const TailLev &g, int c, int &i, int &j, int &k) const {
         int r;
@@ -898,7 +980,72 @@ struct Tail {
             __syncthreads();
         }
     }
+    // Weighted Jacobi value of cell (i,j,k) from the current (old) values.
+    __device__ __forceinline__ T jacobi_value(const TailLev &g, int i, int j, int k) const {
+        T w[6], nb[6];
+        stencil(g, i, j, k, w, nb);
+        T num = T(0), den = T(0);
+#pragma unroll
+        for (int f = 0; f < 2 * D; f++) {
+            num += w[f] * nb[f];
+            den += w[f];
+        }
+        const int o = tix<D>(g, i, j, k);
+        const T gs = VAR ? (num - tf[o]) / den : (num - tf[o]) * T(g.inv_den);
+        return tv[o] + T(omega) * (gs - tv[o]);
+    }
+    // One weighted Jacobi step: all new values first (registers, or the scratch grid
+    // for large grids), then they replace the old ones and push their ghosts.
+    __device__ __forceinline__ void jacobi_step(int lev) const {
+        constexpr int R = 8;
+        const TailLev g = lv[lev];
+        const bool regs = g.ncell <= R * (int)blockDim.x;
+        T nv[R];
+        if (regs) {
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int c = threadIdx.x + r * blockDim.x;
+                if (c < g.ncell) {
+                    int i, j, k;
+                    cell(g, c, i, j, k);
+                    nv[r] = jacobi_value(g, i, j, k);
+                }
+            }
+        } else {
+            for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
+                int i, j, k;
+                cell(g, c, i, j, k);
+                ttmp[tix<D>(g, i, j, k)] = jacobi_value(g, i, j, k);
+            }
+        }
+        __syncthreads();
+        if (regs) {
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int c = threadIdx.x + r * blockDim.x;
+                if (c < g.ncell) {
+                    int i, j, k;
+                    cell(g, c, i, j, k);
+                    tv[tix<D>(g, i, j, k)] = nv[r];
+                    push(tv, g, i, j, k, nv[r], true);
+                }
+            }
+        } else {
+            for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
+                int i, j, k;
+                cell(g, c, i, j, k);
+                const T x = ttmp[tix<D>(g, i, j, k)];
+                tv[tix<D>(g, i, j, k)] = x;
+                push(tv, g, i, j, k, x, true);
+            }
+        }
+        __syncthreads();
+    }
     __device__ __forceinline__ void smooth(int lev) const {
+        if (jac) {
+            jacobi_step(lev);
+            return;
+        }
         sweep(lev, 0);
         sweep(lev, 1);
     }
@@ -1190,13 +1337,15 @@ __global__ void __launch_bounds__(VAR ? 512 : 1024) k_tail(Plane<T> P, DevTables
         if (VAR)
             for (int q = threadIdx.x; q < n; q += blockDim.x) se[q] = P.teps[first + q];
         __syncthreads();
-        const Tail<T, D, VAR> tl{lvs, bcs, red, sv, so, sf, VAR ? se : nullptr, P.tvold + first, top};
+        const Tail<T, D, VAR> tl{lvs, bcs, red, sv, so, sf, VAR ? se : nullptr, P.tvold + first, top,
+                                 P.tv2 ? P.tv2 + first : nullptr, tp.jacobi, tp.omega};
         steps = tl.run(ops, nops, tp);
         for (int q = threadIdx.x; q < g.npad; q += blockDim.x) P.tv[first + g.off + q] = sv[g.off + q];
     } else {
         __syncthreads();
         const Tail<T, D, VAR> tl{lvs, bcs, red, P.tv + first, P.tvold + first, P.tf + first,
-                                 VAR ? P.teps + first : nullptr, nullptr, top};
+                                 VAR ? P.teps + first : nullptr, nullptr, top,
+                                 P.tv2 ? P.tv2 + first : nullptr, tp.jacobi, tp.omega};
         steps = tl.run(ops, nops, tp);
     }
     if (threadIdx.x == 0) steps_out[dm] = steps;
@@ -1214,7 +1363,7 @@ __global__ void __launch_bounds__(512) k_tail_eps(Plane<T> P, DevTables tb, int 
     tail_setup(tb, dm, nt, D, first, lvs, &bcs);
     __syncthreads();
     const Tail<T, D, true> tl{lvs, bcs, red, P.tv + first, P.tvold + first, P.tf + first, P.teps + first,
-                              nullptr, nt - 1};
+                              nullptr, nt - 1, nullptr, 0, 0.0};
     for (int l = nt - 1; l >= 1; l--) {
         const TailLev &gf = lvs[l], &gc = lvs[l - 1];
         for (int c = threadIdx.x; c < gc.ncell; c += blockDim.x) {
@@ -1309,6 +1458,33 @@ __global__ void __launch_bounds__(256) k_ugsrb(Plane<T> P, DevTables tb, UGrid g
     upush<T, D>(P, tb, g, i, j, k, nv);
 }
 
+// Weighted Jacobi step on a large coarse grid: src -> dst (padded tail arrays).
+template <typename T, int D, bool VAR>
+__global__ void __launch_bounds__(256) k_ujacobi(Plane<T> P, const T *src, T *dst, DevTables tb, UGrid g,
+                                                 double omega) {
+    const int64_t n = (int64_t)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1);
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int i = (int)(q % g.n[0]);
+    const int r = (int)(q / g.n[0]);
+    const int j = r % g.n[1], k = D == 3 ? r / g.n[1] : 0;
+    Plane<T> S = P, Q = P;
+    S.tv = const_cast<T *>(src);
+    Q.tv = dst;
+    T w[6], nb[6];
+    ustencil<T, D, VAR>(S, g, i, j, k, w, nb);
+    T num = T(0), den = T(0);
+    for (int f = 0; f < 2 * D; f++) {
+        num += w[f] * nb[f];
+        den += w[f];
+    }
+    const int64_t o = uidx(g, i, j, k, D);
+    const T vc = src[o];
+    const T nv = vc + T(omega) * ((num - P.tf[o]) / den - vc);
+    dst[o] = nv;
+    upush<T, D>(Q, tb, g, i, j, k, nv);
+}
+
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_ughost(Plane<T> P, DevTables tb, UGrid g) {
     const int64_t n = (int64_t)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1);
@@ -1398,6 +1574,13 @@ __global__ void k_fill(T *p, size_t n, T value) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) p[i] = value;
+}
+
+template <typename T>
+__global__ void k_copy(T *dst, const T *src, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) dst[i] = src[i];
 }
 
 // Leaf-ordered user array (x fastest within a block) <-> colour-split block storage.
@@ -1878,6 +2061,38 @@ void K<T>::ucorrect(const Launch &L, const Plane<T> &P, const UGrid &g, const UG
     const unsigned nb = ublocks(ucells(g, L.dim));
     if (L.dim == 3) k_ucorrect<T, 3><<<nb, 256, 0, L.stream>>>(P, L.tb, g, gc);
     else k_ucorrect<T, 2><<<nb, 256, 0, L.stream>>>(P, L.tb, g, gc);
+}
+
+template <typename T>
+void K<T>::copy(const Launch &L, T *dst, const T *src, size_t n) {
+    if (!n) return;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    k_copy<T><<<(unsigned)blocks, 256, 0, L.stream>>>(dst, src, n);
+}
+
+template <typename T>
+void K<T>::jacobi(const Launch &L, const Plane<T> &P, T *dst, T *dstg, int lev, int b0, int nb, uint64_t mask,
+                  bool var, double omega) {
+    if (nb <= 0) return;
+    DISPATCH_DB(L, {
+        constexpr int NC = G<D, BS>::NC;
+        constexpr int TPB = NC < 256 ? NC : 256;
+        if (var) k_jacobi<T, D, BS, true><<<nb, TPB, 0, L.stream>>>(P, dst, dstg, L.tb, lev, b0, mask, omega);
+        else k_jacobi<T, D, BS, false><<<nb, TPB, 0, L.stream>>>(P, dst, dstg, L.tb, lev, b0, mask, omega);
+    });
+}
+
+template <typename T>
+void K<T>::ujacobi(const Launch &L, const Plane<T> &P, const T *src, T *dst, const UGrid &g, bool var, double omega) {
+    const unsigned nb = ublocks(ucells(g, L.dim));
+    if (L.dim == 3) {
+        if (var) k_ujacobi<T, 3, true><<<nb, 256, 0, L.stream>>>(P, src, dst, L.tb, g, omega);
+        else k_ujacobi<T, 3, false><<<nb, 256, 0, L.stream>>>(P, src, dst, L.tb, g, omega);
+    } else {
+        if (var) k_ujacobi<T, 2, true><<<nb, 256, 0, L.stream>>>(P, src, dst, L.tb, g, omega);
+        else k_ujacobi<T, 2, false><<<nb, 256, 0, L.stream>>>(P, src, dst, L.tb, g, omega);
+    }
 }
 
 template <typename T>

@@ -32,6 +32,7 @@ MG_OK, MG_ERR_ARG, MG_ERR_NOT_BALANCED, MG_ERR_DEVICE = 0, -1, -2, -3
 MG_ERR_NOT_CONVERGED, MG_ERR_OOM, MG_ERR_STATE, MG_ERR_NAN = -4, -5, -6, -7
 MG_BC_DIRICHLET, MG_BC_NEUMANN, MG_BC_PERIODIC = 0, 1, 2
 MG_FP64, MG_MIXED = 0, 1
+MG_SMOOTH_GSRB, MG_SMOOTH_JACOBI = 0, 1
 
 
 class mg_bc(ctypes.Structure):
@@ -48,7 +49,7 @@ class mg_params(ctypes.Structure):
                 ("coarse_abs_tol", ctypes.c_double), ("coarse_rel_tol", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("variable_eps", ctypes.c_int32),
                 ("ir_first_fmg", ctypes.c_int32), ("ir_vcycles", ctypes.c_int32), ("graphs", ctypes.c_int32),
-                ("krylov", ctypes.c_int32)]
+                ("krylov", ctypes.c_int32), ("smoother", ctypes.c_int32), ("jacobi_weight", ctypes.c_double)]
 
 
 mg_refine_fn = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
