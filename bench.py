@@ -40,7 +40,7 @@ def _args():
     p.add_argument("--cpu-sample-cycles", type=int, default=1, help="V-cycles after the FMG in the CPU sample")
     p.add_argument("--workload", default="periodic256",
                    choices=["periodic256", "dirichlet2d", "amr-literal", "amr-nested", "varcoef-nested", "batch",
-                            "tree-build"],
+                            "tree-build", "paper-scaling"],
                    help="periodic256 is the benchmark line; the others print report lines")
     p.add_argument("--max-cycles", type=int, default=60)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -223,6 +223,55 @@ def report(a):
         out["value"] = out["fp64"]["value"]
         out["ms_per_step"] = out["fp64"]["time_to_tol_ms"]
         out["dtype"] = "f64"
+        print(json.dumps(out), flush=True)
+        return
+    if a.workload == "paper-scaling":
+        # the paper's timing problem (Sec. 3.3): lap(phi) = 1 on the unit cube, phi = 0 on
+        # the boundary, 16^3 blocks, Jacobi with 2 + 2 steps, time per V-cycle and per FMG
+        # cycle averaged over 100 cycles; uniform 512^3 and 1024^3, and five levels of
+        # 512^3 cells each with the refinements centred
+        out = dict(base, metric="time per V-cycle and per FMG cycle (mean of 100)", unit="ms",
+                   higher_is_better=False, dtype="f64",
+                   config={"workload": "lap(phi)=1, phi=0 on the unit cube, 16^3 blocks, Jacobi 2+2 (weight 2/3)"})
+        ncyc = 100
+
+        def centred(levels):
+            def pred(dm, lev, o, bs):
+                # blocks inside the centred cube of side 2^-(lev+1) (block origin in cells)
+                n = 512 << lev
+                lo, hi = n // 2 - n // 2 ** (lev + 2), n // 2 + n // 2 ** (lev + 2)
+                return lev < levels - 1 and all(lo <= o[q] and o[q] + bs <= hi for q in range(3))
+            return pred
+
+        cases = [("uniform_512", 512, 0, None), ("uniform_1024", 1024, 0, None),
+                 ("refined_5x512", 512, 4, centred(5))]
+        for name, n, mr, pred in cases:
+            d = mg.Domain(3, [n] * 3, [0, 0, 0], [1, 1, 1], [mg.MG_BC_DIRICHLET] * 6)
+            p = mg.default_params(smoother=mg.MG_SMOOTH_JACOBI)
+            t = mg.Tree([d], bs=16, max_refine=mr, refine=pred, params=p)
+            t.set_rhs(torch.ones(t.n_leaf, dtype=torch.float64, device="cuda"))
+            res = {"leaf_cells": t.n_leaf, "levels": t.num_levels()}
+            t.vcycle(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t.vcycle(ncyc)
+            torch.cuda.synchronize()
+            res["ms_per_vcycle"] = (time.perf_counter() - t0) * 1e3 / ncyc
+            res["residual_after_vcycles"] = t.residual_norm()[0]
+            t.set_phi(torch.zeros(t.n_leaf, dtype=torch.float64, device="cuda"))
+            t.fmg(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t.fmg(ncyc)
+            torch.cuda.synchronize()
+            res["ms_per_fmg"] = (time.perf_counter() - t0) * 1e3 / ncyc
+            res["residual_after_fmg"] = t.residual_norm()[0]
+            out[name] = res
+            print(name, res, file=sys.stderr, flush=True)
+            del t
+            torch.cuda.empty_cache()
+        out["value"] = out["uniform_1024"]["ms_per_vcycle"]
+        out["ms_per_step"] = out["uniform_1024"]["ms_per_vcycle"]
         print(json.dumps(out), flush=True)
         return
     if a.workload == "tree-build":
