@@ -40,7 +40,7 @@ def _args():
     p.add_argument("--cpu-sample-cycles", type=int, default=1, help="V-cycles after the FMG in the CPU sample")
     p.add_argument("--workload", default="periodic256",
                    choices=["periodic256", "dirichlet2d", "amr-literal", "amr-nested", "varcoef-nested", "batch",
-                            "tree-build", "paper-scaling"],
+                            "tree-build", "paper-scaling", "convergence"],
                    help="periodic256 is the benchmark line; the others print report lines")
     p.add_argument("--max-cycles", type=int, default=60)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -272,6 +272,39 @@ def report(a):
             torch.cuda.empty_cache()
         out["value"] = out["uniform_1024"]["ms_per_vcycle"]
         out["ms_per_step"] = out["uniform_1024"]["ms_per_vcycle"]
+        print(json.dumps(out), flush=True)
+        return
+    if a.workload == "convergence":
+        # the paper's convergence test (Sec. 3.1): residual and error per FMG iteration
+        # on 64^3 cells, uniform or with two centred / corner refinement levels
+        out = dict(base, metric="residual and error per FMG iteration", unit="-", dtype="f64 and mixed",
+                   config={"workload": "eq. poisson-conv, 64^3 base, FMG V(2,2)"})
+        for grid in ("uniform", "center", "corner"):
+            w = W.x1(grid, base=64)
+            for prec, key in ((mg.MG_FP64, "fp64"), (mg.MG_MIXED, "mixed")):
+                t = _tree_of(w, prec, mg)
+                f, _, lay = _inputs(w, t)
+                d = w.domains[0]
+                x = W.cell_centres(lay[:, 1:], d)
+                vol = np.prod(W.cell_widths(lay[:, 1:], d), axis=1)
+                sol = W.x1_solution(x)
+                fh = f.cpu().numpy()
+                fmax, fl2 = np.abs(fh).max(), np.sqrt(np.sum(vol * fh * fh))
+                t.set_rhs(f)
+                rows = []
+                for it in range(12):
+                    t.fmg()
+                    rm, rl = t.residual_norm()
+                    e = t.get_phi() - sol
+                    rows.append({"res_inf": rm * fmax, "res_l2": rl * fl2, "err_inf": float(np.abs(e).max()),
+                                 "err_l2": float(np.sqrt(np.sum(vol * e * e)))})
+                out[f"{grid}_{key}"] = {"leaf_cells": t.n_leaf, "iterations": rows}
+                del t
+        u, c, k = out["uniform_fp64"]["iterations"], out["center_fp64"]["iterations"], out["corner_fp64"]["iterations"]
+        out["max_error_ratio_uniform_over_center"] = u[-1]["err_inf"] / c[-1]["err_inf"]
+        out["l2_error_ratio_corner_over_uniform"] = k[-1]["err_l2"] / u[-1]["err_l2"]
+        out["value"] = out["max_error_ratio_uniform_over_center"]
+        out["ms_per_step"] = None
         print(json.dumps(out), flush=True)
         return
     if a.workload == "tree-build":

@@ -228,3 +228,63 @@ def config5(sizes: Sequence[int] = CONFIG5_SIZES) -> Workload:
         return 1e-3 * np.prod(np.sin(np.pi * x), axis=1)
 
     return Workload("diffsolve3d_batch6", doms, variable_eps=True, rhs=rhs, eps=eps, target=target)
+
+
+# ------------------------------------------------------- convergence test (Sec. 3.1)
+X1_N = np.array([1.0, 2.0, 3.0])
+
+
+def x1_solution(x: np.ndarray) -> np.ndarray:
+    """phi_sol = cos(pi n.x) + 10 exp(-100 |x|^2), n = (1, 2, 3) (eq. poisson-conv)."""
+    return np.cos(np.pi * x @ X1_N) + 10.0 * np.exp(-100.0 * np.sum(x * x, axis=1))
+
+
+def x1_laplacian(x: np.ndarray) -> np.ndarray:
+    """Analytic Laplacian of x1_solution."""
+    r2 = np.sum(x * x, axis=1)
+    return (-np.pi ** 2 * np.dot(X1_N, X1_N) * np.cos(np.pi * x @ X1_N)
+            + 10.0 * np.exp(-100.0 * r2) * (-600.0 + 40000.0 * r2))
+
+
+def x1(grid: str = "uniform", base: int = 64) -> Workload:
+    """The paper's convergence test (Sec. 3.1): unit cube centred at the origin,
+    lap(phi) = f with f the analytic Laplacian of x1_solution and Dirichlet values
+    from the solution.  grid: 'uniform' (base^3), 'center' or 'corner' (two extra
+    levels covering 0.5^3 and 0.25^3, each again base^3 cells, centred at the origin
+    or around (-0.25, -0.25, -0.25)).
+
+    The library takes one Dirichlet value per face, so the varying boundary values
+    enter through the right-hand side: with the reflection ghost g = 2b - phi_i the
+    equation of a boundary cell equals the one with g = -phi_i (homogeneous value) and
+    f - 2 b / h^2 per boundary face (b = phi_sol at the face centre).  The discrete
+    problem and its residual at every leaf cell are the same."""
+    dom = Domain(3, [base] * 3, [-0.5] * 3, [0.5] * 3, [DIRICHLET] * 6)
+    if grid == "center":
+        boxes = {0: (-0.25, 0.25), 1: (-0.125, 0.125)}
+    elif grid == "corner":
+        boxes = {0: (-0.5, 0.0), 1: (-0.375, -0.125)}
+    else:
+        boxes = {}
+
+    def rule(d, level, origin, bs):
+        if level not in boxes:
+            return False
+        lo, hi = boxes[level]
+        h = 1.0 / (base * 2 ** level)
+        return all(lo - 1e-12 <= -0.5 + origin[q] * h and -0.5 + (origin[q] + bs) * h <= hi + 1e-12
+                   for q in range(3))
+
+    def rhs(i, lay):
+        x = cell_centres(lay, dom)
+        h = cell_widths(lay, dom)
+        f = x1_laplacian(x)
+        for a in range(3):
+            for side, face in ((0, -0.5), (1, 0.5)):
+                on = np.isclose(x[:, a] + (h[:, a] / 2 if side else -h[:, a] / 2), face)
+                xb = x[on].copy()
+                xb[:, a] = face
+                f[on] -= 2.0 * x1_solution(xb) / h[on, a] ** 2
+        return f
+
+    return Workload(f"convergence_{grid}_{base}", [dom], max_refine=len(boxes), refine=rule if boxes else None,
+                    rhs=rhs, note="phi_sol = cos(pi n.x) + 10 exp(-100|x|^2), n = (1,2,3)")

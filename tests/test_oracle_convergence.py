@@ -1,0 +1,50 @@
+"""The paper's convergence test (Sec. 3.1, eq. poisson-conv) on the reference solver:
+64^3 cells, uniform or with two centred / corner refinement levels.  Pins the numbers
+the paper states in the text: after two FMG iterations the error is at the
+discretisation level, the centred refinement lowers the max-norm error by a factor of
+about 20 (the paper reports 20, slightly above the 16 of second order), and the corner
+refinement leaves the errors nearly unchanged."""
+import numpy as np
+import pytest
+
+from helpers import oracle_trees
+from paper_1901_11370_amd import workloads as W
+
+
+def _errors(grid, iters=2):
+    w = W.x1(grid, base=64)
+    o = oracle_trees(w)[0]
+    lay = o.leaf_layout()
+    o.set_rhs(w.rhs(0, lay))
+    d = w.domains[0]
+    x = W.cell_centres(lay, d)
+    vol = np.prod(W.cell_widths(lay, d), axis=1)
+    sol = W.x1_solution(x)
+    out = []
+    for _ in range(iters):
+        o.fmg()
+        e = o.get_phi() - sol
+        out.append((np.abs(e).max(), np.sqrt(np.sum(vol * e * e))))
+    return out
+
+
+@pytest.fixture(scope="module")
+def errs():
+    return {g: _errors(g, 3 if g == "uniform" else 2) for g in ("uniform", "center", "corner")}
+
+
+def test_error_reaches_discretisation_level_in_two_fmg_iterations(errs):
+    (i2, l2), (i3, l3) = errs["uniform"][1], errs["uniform"][2]
+    assert abs(i3 - i2) <= 0.02 * i2 and abs(l3 - l2) <= 0.02 * l2
+
+
+def test_centred_refinement_reduces_max_error_about_twenty_fold(errs):
+    ratio = errs["uniform"][1][0] / errs["center"][1][0]
+    print("max-norm error ratio uniform / centred", ratio)
+    assert 16.0 <= ratio <= 25.0
+
+
+def test_corner_refinement_hardly_changes_the_errors(errs):
+    u, c = errs["uniform"][1], errs["corner"][1]
+    assert abs(c[1] - u[1]) <= 0.1 * u[1]          # L2
+    assert c[0] <= 1.5 * u[0]                       # max norm
