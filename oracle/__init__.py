@@ -74,6 +74,7 @@ def lib():
         L.og_correct_level.argtypes = [vp, ctypes.c_int]
         L.og_smooth_level.argtypes = [vp, ctypes.c_int, ctypes.c_int]
         L.og_set_smoother.argtypes = [vp, ctypes.c_int, d]
+        L.og_set_lambda.argtypes = [vp, d]
         _lib = L
     return _lib
 
@@ -134,6 +135,9 @@ class OracleTree:
 
     def set_smoother(self, kind, omega=2.0 / 3.0):
         lib().og_set_smoother(self._h, kind, omega)
+
+    def set_lambda(self, lam):
+        lib().og_set_lambda(self._h, lam)
 
     @property
     def num_levels(self):

@@ -53,6 +53,7 @@ struct og_tree {
     double abs_tol, rel_tol;
     int smoother;    /* OG_SMOOTH_GSRB or OG_SMOOTH_JACOBI */
     double omega;    /* Jacobi weight */
+    double lambda;   /* Helmholtz term: L phi = div(eps grad phi) - lambda phi, lambda >= 0 */
     int *leaf;       /* leaf blocks in canonical order */
     int nleaf;
     int last_coarse_steps;
@@ -233,7 +234,7 @@ og_tree *og_create(int dim, const int32_t *base_cells, const double *lo, const d
         t->hi[d] = d < dim ? hi[d] : 1.0;
     }
     t->n_down = 2; t->n_up = 2; t->n_max = 1000; t->abs_tol = 0.0; t->rel_tol = 1e-8;
-    t->smoother = OG_SMOOTH_GSRB; t->omega = 2.0 / 3.0;
+    t->smoother = OG_SMOOTH_GSRB; t->omega = 2.0 / 3.0; t->lambda = 0.0;
     t->refine = refine; t->ud = ud;
 
     /* Added coarse grids (Sec. 2.5): halve the grid while every halved size still
@@ -358,6 +359,8 @@ void og_set_params(og_tree *t, int n_down, int n_up, int n_max, double abs_tol, 
     t->n_down = n_down; t->n_up = n_up; t->n_max = n_max;
     t->abs_tol = abs_tol; t->rel_tol = rel_tol;
 }
+
+void og_set_lambda(og_tree *t, double lambda) { t->lambda = lambda; }
 
 void og_set_smoother(og_tree *t, int kind, double omega) {
     t->smoother = kind;
@@ -527,7 +530,7 @@ static double apply_L(const og_tree *t, int l, const OBlock *B, int i, int j, in
             sum += ih2 * (harmonic(e[p], e[pm]) * (v[pm] - v[p]) + harmonic(e[p], e[pp]) * (v[pp] - v[p]));
         }
     }
-    return sum;
+    return sum - t->lambda * v[p];
 }
 
 /* Gauss-Seidel local solve (Sec. 2.2): the cell's equation solved for phi_i with its
@@ -555,7 +558,7 @@ static double gs_value(const og_tree *t, int l, const OBlock *B, int i, int j, i
             den += wm + wp;
         }
     }
-    return (num - B->fld[F_F][p]) / den;
+    return (num - B->fld[F_F][p]) / (den + t->lambda);
 }
 
 /* ---------------------------------------------------------------- smoother */
@@ -732,7 +735,7 @@ static int all_periodic(const og_tree *t) {
  * of f is first removed on this level so that the singular system is consistent. */
 static void coarse_solve(og_tree *t) {
     const OLevel *L = &t->lev[0];
-    if (all_periodic(t)) {
+    if (all_periodic(t) && t->lambda == 0.0) {
         double s = 0.0;
         long cnt = 0;
         for (int q = 0; q < L->n; q++) {

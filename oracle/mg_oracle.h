@@ -43,6 +43,8 @@ void og_set_params(og_tree *t, int n_down, int n_up, int n_max, double abs_tol, 
 /* Smoother: red-black Gauss-Seidel (default) or weighted Jacobi with weight omega. */
 enum { OG_SMOOTH_GSRB = 0, OG_SMOOTH_JACOBI = 1 };
 void og_set_smoother(og_tree *t, int kind, double omega);
+/* Helmholtz term (Sec. 2.1 equation list): L phi = div(eps grad phi) - lambda phi. */
+void og_set_lambda(og_tree *t, double lambda);
 
 /* Structure queries. */
 int og_num_levels(const og_tree *t);
