@@ -1,7 +1,8 @@
 /*
  * mg.h -- C ABI of the MI355X multigrid library for quadtree/octree block grids.
  *
- * Solves div(eps grad phi) = f (the paper's eq. poisson) on one or more independent
+ * Solves div(eps grad phi) - lambda phi = f (the paper's eq. poisson, and its Helmholtz
+ * form with lambda >= 0) on one or more independent
  * domains, each a quadtree (2D) or octree (3D) of bs^d-cell blocks, with the
  * second-order cell-centred operators of Sec. 2.2 (eq. poisson-2d, poisson-2d-vcoeff),
  * red-black Gauss-Seidel smoothing, the transfer operators of Sec. 2.3, and FAS
@@ -104,6 +105,8 @@ typedef struct {
                                  one smoothing step */
     double jacobi_weight;     /* Jacobi weight in (0, 1]; default 2/3 (not given in the
                                  paper) */
+    double helmholtz_lambda;  /* lambda >= 0 of the Helmholtz form div(eps grad phi) -
+                                 lambda phi = f (Sec. 2.1 equation list); default 0 */
 } mg_params;
 
 /* Fills p with the paper's defaults (Sec. 2.4) and FP64 precision. */

@@ -176,6 +176,7 @@ size_t plan(mg_tree *t, char *base) {
         tb.bcv = (const double *)P(o_bcv);
         tb.tail_off = (const int64_t *)P(o_toff);
         tb.tail_top = (const int32_t *)P(o_ttop);
+        tb.lambda = t->prm.helmholtz_lambda;
         t->tb0 = tb;
         t->tb0.bcv = (const double *)P(o_bc0);
         t->d_parents.assign(T.nlev, nullptr);
@@ -753,6 +754,7 @@ int mg_default_params(mg_params *p) {
     p->krylov = 0;
     p->smoother = MG_SMOOTH_GSRB;
     p->jacobi_weight = 2.0 / 3.0;
+    p->helmholtz_lambda = 0.0;
     return MG_OK;
 }
 
@@ -768,7 +770,7 @@ int mg_tree_create(const mg_domain *domains, int n_domains, int block_size, int 
         (p.precision != MG_FP64 && p.precision != MG_MIXED) || p.ir_vcycles < 1 || (p.graphs != 0 && p.graphs != 1) ||
         p.krylov < 0 || p.krylov > 64 || (p.krylov > 0 && p.precision != MG_MIXED) ||
         (p.smoother != MG_SMOOTH_GSRB && p.smoother != MG_SMOOTH_JACOBI) ||
-        !(p.jacobi_weight > 0.0 && p.jacobi_weight <= 1.0)) {
+        !(p.jacobi_weight > 0.0 && p.jacobi_weight <= 1.0) || !(p.helmholtz_lambda >= 0.0)) {
         delete t;
         return MG_ERR_ARG;
     }

@@ -34,6 +34,7 @@ struct DevTables {
     const double *bcv;        // [ndom][6] boundary values (or zeros: homogeneous)
     const int64_t *tail_off;  // [ndom][MAXLEV] offset of a tail level's padded array (cells)
     const int32_t *tail_top;  // [ndom] highest tail level run by the one-workgroup kernel
+    double lambda;            // Helmholtz term: L phi = div(eps grad phi) - lambda phi
 };
 
 // Tail levels with more cells than this (per domain) run as multi-workgroup launches;

@@ -126,19 +126,21 @@ struct Stager {
 
 struct Spacing {
     double ih2[3];
+    double lam;   // Helmholtz term
 };
 
 __device__ __forceinline__ Spacing spacing(const DevTables &tb, int dm, int lev) {
     const double *h = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
     Spacing s;
     for (int a = 0; a < 3; a++) s.ih2[a] = 1.0 / (h[a] * h[a]);
+    s.lam = tb.lambda;
     return s;
 }
 
 // (L v) and the Gauss-Seidel numerator/denominator at one cell of a block.
 template <typename T, int D, int BS, bool VAR>
 struct Stencil {
-    T nb[6], w[6], vc;
+    T nb[6], w[6], vc, lam;
     __device__ __forceinline__ void load(const Plane<T> &P, int64_t b, int i, int j, int k,
                                          const Spacing &s, bool need_center) {
         nb[0] = ld<D, BS>(P.v, P.vg, b, i - 1, j, k);
@@ -150,6 +152,7 @@ struct Stencil {
             nb[5] = ld<D, BS>(P.v, P.vg, b, i, j, k + 1);
         }
         vc = need_center ? P.v[b * G<D, BS>::NC + G<D, BS>::in(i, j, k)] : T(0);
+        lam = T(s.lam);
         if (!VAR) {
             for (int f = 0; f < 2 * D; f++) w[f] = T(s.ih2[f / 2]);
         } else {
@@ -169,10 +172,10 @@ struct Stencil {
     __device__ __forceinline__ T Lv() const {
         T s = T(0);
         for (int f = 0; f < 2 * D; f++) s += w[f] * (nb[f] - vc);
-        return s;
+        return s - lam * vc;
     }
     __device__ __forceinline__ T gs(T fval) const {
-        T num = T(0), den = T(0);
+        T num = T(0), den = lam;
         for (int f = 0; f < 2 * D; f++) {
             num += w[f] * nb[f];
             den += w[f];
@@ -340,7 +343,7 @@ __global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev,
             gho[4] = k == 0;      off[4] = gho[4] ? 4 * HF + j * g::RH + (i >> 1) : (row - BS) * g::RH + (i >> 1);
             gho[5] = k == BS - 1; off[5] = gho[5] ? 5 * HF + j * g::RH + (i >> 1) : (row + BS) * g::RH + (i >> 1);
         }
-        T num = T(0), den = T(0);
+        T num = T(0), den = T(tb.lambda);
         const T fval = fr[m];
         if (!VAR) {
 #pragma unroll
@@ -410,7 +413,7 @@ __global__ void __launch_bounds__(256) k_jacobi(Plane<T> P, T *__restrict__ dst,
             nb[4] = k > 0 ? s_v[g::in(i, j, k - 1)] : s_v[g::NC + g::gh(4, i, j)];
             nb[5] = k < BS - 1 ? s_v[g::in(i, j, k + 1)] : s_v[g::NC + g::gh(5, i, j)];
         }
-        T num = T(0), den = T(0);
+        T num = T(0), den = T(tb.lambda);
         if (!VAR) {
 #pragma unroll
             for (int f = 0; f < 2 * D; f++) {
@@ -646,6 +649,7 @@ __global__ void __launch_bounds__(256) k_restrict(Plane<T> P, DevTables tb, int 
 #pragma unroll
                     for (int f = 0; f < 2 * D; f++) lv += harm(e0, en[f]) * ih2[f >> 1] * (nb[f] - vc);
                 }
+                lv -= T(tb.lambda) * vc;
                 sr += pre[m][q] - lv;
             }
         }
@@ -820,7 +824,8 @@ struct TailLev {
     int ghost_pass;    // periodic axis with an odd cell count
     float inv_rh, inv_n0, inv_n1;
     double h[3], ih2[3];
-    double inv_den;    // 1 / (2 sum ih2): the constant-coefficient diagonal
+    double inv_den;    // 1 / (2 sum ih2 + lambda): the constant-coefficient diagonal
+    double lam;        // Helmholtz term
 };
 struct TailBC {
     int kind[6];
@@ -950,7 +955,7 @@ struct Tail {
         T s = T(0);
 #pragma unroll
         for (int f = 0; f < 2 * D; f++) s += w[f] * (nb[f] - vc);
-        return s;
+        return s - T(g.lam) * vc;
     }
 
     // One colour of Gauss-Seidel on grid lev, then a barrier.
@@ -963,7 +968,7 @@ struct Tail {
             if (!slot(g, s, colour, i, j, k)) continue;
             T w[6], nb[6];
             stencil(g, i, j, k, w, nb);
-            T num = T(0), den = T(0);
+            T num = T(0), den = T(g.lam);
 #pragma unroll
             for (int f = 0; f < 2 * D; f++) {
                 num += w[f] * nb[f];
@@ -984,7 +989,7 @@ struct Tail {
     __device__ __forceinline__ T jacobi_value(const TailLev &g, int i, int j, int k) const {
         T w[6], nb[6];
         stencil(g, i, j, k, w, nb);
-        T num = T(0), den = T(0);
+        T num = T(0), den = T(g.lam);
 #pragma unroll
         for (int f = 0; f < 2 * D; f++) {
             num += w[f] * nb[f];
@@ -1163,7 +1168,7 @@ struct Tail {
     // f first.
     __device__ __forceinline__ int coarse_solve(const TailParams &tp) const {
         const TailLev g = lv[0];
-        bool per = true;
+        bool per = g.lam == 0.0;   // the regular Helmholtz operator needs no mean removal
         for (int f = 0; f < 2 * D; f++) per = per && bc.kind[f] == MG_BC_PERIODIC;
         if (per) {
             double s = 0.0;
@@ -1290,7 +1295,8 @@ __device__ __forceinline__ void tail_setup(const DevTables &tb, int dm, int nlev
             g.h[a] = 1.0;
             g.ih2[a] = 0.0;
         }
-        g.inv_den = 1.0 / (2.0 * (g.ih2[0] + g.ih2[1] + g.ih2[2]));
+        g.lam = tb.lambda;
+        g.inv_den = 1.0 / (2.0 * (g.ih2[0] + g.ih2[1] + g.ih2[2]) + g.lam);
         lv[l] = g;
     }
     if (threadIdx.x < 6) {
@@ -1447,7 +1453,7 @@ __global__ void __launch_bounds__(256) k_ugsrb(Plane<T> P, DevTables tb, UGrid g
     const int i = 2 * pos + ((j + k + colour) & 1);
     T w[6], nb[6];
     ustencil<T, D, VAR>(P, g, i, j, k, w, nb);
-    T num = T(0), den = T(0);
+    T num = T(0), den = T(tb.lambda);
     for (int f = 0; f < 2 * D; f++) {
         num += w[f] * nb[f];
         den += w[f];
@@ -1473,7 +1479,7 @@ __global__ void __launch_bounds__(256) k_ujacobi(Plane<T> P, const T *src, T *ds
     Q.tv = dst;
     T w[6], nb[6];
     ustencil<T, D, VAR>(S, g, i, j, k, w, nb);
-    T num = T(0), den = T(0);
+    T num = T(0), den = T(tb.lambda);
     for (int f = 0; f < 2 * D; f++) {
         num += w[f] * nb[f];
         den += w[f];
@@ -1511,7 +1517,7 @@ __global__ void __launch_bounds__(256) k_ufas(Plane<T> P, DevTables tb, UGrid g)
     T w[6], nb[6];
     ustencil<T, D, VAR>(P, g, i, j, k, w, nb);
     const T vc = P.tv[g.off + q];
-    T lv = T(0);
+    T lv = -T(tb.lambda) * vc;
     for (int f = 0; f < 2 * D; f++) lv += w[f] * (nb[f] - vc);
     P.tf[g.off + q] += lv;
 }
@@ -1531,7 +1537,7 @@ __global__ void __launch_bounds__(256) k_urestrict(Plane<T> P, DevTables tb, UGr
         ustencil<T, D, VAR>(P, g, i, j, k, w, nb);
         const int64_t o = uidx(g, i, j, k, D);
         const T vc = P.tv[o];
-        T lv = T(0);
+        T lv = -T(tb.lambda) * vc;
         for (int f = 0; f < 2 * D; f++) lv += w[f] * (nb[f] - vc);
         sv += vc;
         sr += P.tf[o] - lv;
@@ -1694,6 +1700,7 @@ __global__ void __launch_bounds__(256) k_norm(Plane<double> P, DevTables tb, dou
             }
             for (int f = 0; f < 2 * D; f++) lv += harm(e0, en[f]) * ih2[f >> 1] * (nb[f] - vc);
         }
+        lv -= tb.lambda * vc;
         const double fv = fr[m];
         const double r = fv - lv;
         if (fabs(r) > mr || r != r) mr = fabs(r);

@@ -49,7 +49,8 @@ class mg_params(ctypes.Structure):
                 ("coarse_abs_tol", ctypes.c_double), ("coarse_rel_tol", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("variable_eps", ctypes.c_int32),
                 ("ir_first_fmg", ctypes.c_int32), ("ir_vcycles", ctypes.c_int32), ("graphs", ctypes.c_int32),
-                ("krylov", ctypes.c_int32), ("smoother", ctypes.c_int32), ("jacobi_weight", ctypes.c_double)]
+                ("krylov", ctypes.c_int32), ("smoother", ctypes.c_int32), ("jacobi_weight", ctypes.c_double),
+                ("helmholtz_lambda", ctypes.c_double)]
 
 
 mg_refine_fn = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,

@@ -24,6 +24,8 @@ def _run(w, script, tol=TOL, remove_mean=False, **params):
             o.set_smoother(o.JACOBI, params.get("jacobi_weight", 2.0 / 3.0))
         if "n_down" in params or "n_up" in params:
             o.set_params(n_down=params.get("n_down", 2), n_up=params.get("n_up", 2))
+        if "helmholtz_lambda" in params:
+            o.set_lambda(params["helmholtz_lambda"])
     f, e = inputs(w, t)
     if w.variable_eps:
         t.set_eps(np.concatenate(e))
@@ -250,3 +252,39 @@ def test_jacobi_smoother(case):
         g = W.Gaussians(np.array([[0.7, 0.5, 0.4]]), np.array([5.0]), np.array([0.15]))
         w = W.Workload("jacbig", [dom], bs=16, rhs=lambda i, lay: g(W.cell_centres(lay, dom)))
         _run(w, "vfv", smoother=1, n_down=1, n_up=2)
+
+
+# ------------------------------------------------------------ Helmholtz term
+@pytest.mark.parametrize("case", ["periodic3d", "amr_var", "forest_jacobi", "mixed_amr"])
+def test_helmholtz(case):
+    if case == "periodic3d":
+        # regular operator: the constant part of f is kept (no mean removal)
+        w = W.config2(n=64)
+        f0 = w.rhs
+        w.rhs = lambda i, lay: f0(i, lay) + 0.3
+        _run(w, "fvv", helmholtz_lambda=40.0)
+    elif case == "amr_var":
+        w = W.config4(nested=False)
+        w.domains[0].base_cells = [32, 32, 32]
+        _run(w, "fvv", helmholtz_lambda=500.0)
+    elif case == "forest_jacobi":
+        w = W.config5(sizes=(32, 48))
+        _run(w, "vfv", helmholtz_lambda=100.0, smoother=1)
+    else:
+        _mixed_vs_reference_l(W.config3(nested=False, base=32), 1e-8, 250.0)
+
+
+def _mixed_vs_reference_l(w, tol, lam):
+    import torch
+    t = gpu_tree(w, precision=1, helmholtz_lambda=lam)
+    refs = oracle_trees(w)
+    f, e = inputs(w, t)
+    t.set_rhs(torch.from_numpy(np.concatenate(f)).cuda())
+    cycles, rc = t.solve(rel_tol=1e-10, max_cycles=40)
+    for o, fi in zip(refs, f):
+        o.set_lambda(lam)
+        o.set_rhs(fi)
+        o.solve(rel_tol=1e-12, max_cycles=60)
+    errs = [rel_err(p, o.get_phi()) for p, o in zip(split(t, t.get_phi()), refs)]
+    print("mixed helmholtz", cycles, errs, flush=True)
+    assert rc == 0 and max(errs) <= tol
