@@ -40,7 +40,7 @@ def _args():
     p.add_argument("--cpu-sample-cycles", type=int, default=1, help="V-cycles after the FMG in the CPU sample")
     p.add_argument("--workload", default="periodic256",
                    choices=["periodic256", "dirichlet2d", "amr-literal", "amr-nested", "varcoef-nested", "batch",
-                            "tree-build", "paper-scaling", "convergence"],
+                            "tree-build", "paper-scaling", "convergence", "helmholtz"],
                    help="periodic256 is the benchmark line; the others print report lines")
     p.add_argument("--max-cycles", type=int, default=60)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -143,9 +143,10 @@ def cpu_baseline(w, sample_cycles):
                       f"({o.n_leaf} leaf cells), {dt:.2f} s on one host thread"}
 
 
-def _tree_of(w, precision, mg, krylov=0):
+def _tree_of(w, precision, mg, krylov=0, helmholtz_lambda=0.0):
     doms = [mg.Domain(d.dim, d.base_cells, d.lo, d.hi, d.bc_kind, list(d.bc_value)) for d in w.domains]
-    p = mg.default_params(precision=precision, variable_eps=1 if w.variable_eps else 0, krylov=krylov)
+    p = mg.default_params(precision=precision, variable_eps=1 if w.variable_eps else 0, krylov=krylov,
+                          helmholtz_lambda=helmholtz_lambda)
     return mg.Tree(doms, bs=w.bs, max_refine=w.max_refine, refine=w.refine, params=p)
 
 
@@ -188,9 +189,16 @@ def report(a):
                    final_rel_residual=t.residual_norm()[0])
         print(json.dumps(out), flush=True)
         return
-    if a.workload in ("amr-literal", "amr-nested", "varcoef-nested"):
-        w = W.config3(nested=a.workload != "amr-literal") if a.workload != "varcoef-nested" else W.config4(nested=True)
-        out = dict(base, metric="time-to-1e-10 residual", config={"workload": w.name})
+    if a.workload in ("amr-literal", "amr-nested", "varcoef-nested", "helmholtz"):
+        lam = 0.0
+        if a.workload == "helmholtz":
+            # the Helmholtz form on the benchmark grid: lambda = 100
+            w, lam = W.config2(n=256), 100.0
+        elif a.workload == "varcoef-nested":
+            w = W.config4(nested=True)
+        else:
+            w = W.config3(nested=a.workload != "amr-literal")
+        out = dict(base, metric="time-to-1e-10 residual", config={"workload": w.name, "helmholtz_lambda": lam})
         legs = [(mg.MG_FP64, "fp64", 0), (mg.MG_MIXED, "mixed", 0)]
         if w.variable_eps:
             # the coefficient jump stalls the plain cycles: FGMRES refinement as well
@@ -200,7 +208,7 @@ def report(a):
         for prec, key, kry in legs:
             # FGMRES counts every preconditioning solve as a cycle
             MAX_CYCLES = 4 * plain_max if kry else plain_max
-            t = _tree_of(w, prec, mg, krylov=kry)
+            t = _tree_of(w, prec, mg, krylov=kry, helmholtz_lambda=lam)
             f, e, lay = _inputs(w, t)
             if e is not None:
                 t.set_eps(e)
