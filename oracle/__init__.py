@@ -75,6 +75,8 @@ def lib():
         L.og_smooth_level.argtypes = [vp, ctypes.c_int, ctypes.c_int]
         L.og_set_smoother.argtypes = [vp, ctypes.c_int, d]
         L.og_set_lambda.argtypes = [vp, d]
+        L.og_set_axisymmetric.argtypes = [vp, ctypes.c_int]
+        L.og_set_axisymmetric.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -138,6 +140,10 @@ class OracleTree:
 
     def set_lambda(self, lam):
         lib().og_set_lambda(self._h, lam)
+
+    def set_axisymmetric(self, on=True):
+        if lib().og_set_axisymmetric(self._h, 1 if on else 0) != 0:
+            raise ValueError("axisymmetric form needs a 2D domain with lo[0] >= 0")
 
     @property
     def num_levels(self):

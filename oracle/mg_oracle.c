@@ -54,6 +54,7 @@ struct og_tree {
     int smoother;    /* OG_SMOOTH_GSRB or OG_SMOOTH_JACOBI */
     double omega;    /* Jacobi weight */
     double lambda;   /* Helmholtz term: L phi = div(eps grad phi) - lambda phi, lambda >= 0 */
+    int axisym;      /* 2D axisymmetric: x is the radius r, y the axis z */
     int *leaf;       /* leaf blocks in canonical order */
     int nleaf;
     int last_coarse_steps;
@@ -234,7 +235,7 @@ og_tree *og_create(int dim, const int32_t *base_cells, const double *lo, const d
         t->hi[d] = d < dim ? hi[d] : 1.0;
     }
     t->n_down = 2; t->n_up = 2; t->n_max = 1000; t->abs_tol = 0.0; t->rel_tol = 1e-8;
-    t->smoother = OG_SMOOTH_GSRB; t->omega = 2.0 / 3.0; t->lambda = 0.0;
+    t->smoother = OG_SMOOTH_GSRB; t->omega = 2.0 / 3.0; t->lambda = 0.0; t->axisym = 0;
     t->refine = refine; t->ud = ud;
 
     /* Added coarse grids (Sec. 2.5): halve the grid while every halved size still
@@ -361,6 +362,12 @@ void og_set_params(og_tree *t, int n_down, int n_up, int n_max, double abs_tol, 
 }
 
 void og_set_lambda(og_tree *t, double lambda) { t->lambda = lambda; }
+
+int og_set_axisymmetric(og_tree *t, int on) {
+    if (on && (t->dim != 2 || t->lo[0] < 0.0)) return -1;
+    t->axisym = on != 0;
+    return 0;
+}
 
 void og_set_smoother(og_tree *t, int kind, double omega) {
     t->smoother = kind;
@@ -512,6 +519,21 @@ void og_fill_ghosts_level(og_tree *t, int l) {
 
 static double harmonic(double a, double b) { return 2.0 * a * b / (a + b); }
 
+/* Face weights of axis d at cell (i,j,k) of block B: h_d^-2 times, in the 2D
+ * axisymmetric form (Sec. 2.1: (1/r) d/dr (r dphi/dr) + d2phi/dz2, finite volumes), the
+ * ratio of the face radius to the cell-centre radius on the r axis. */
+static void face_weights(const og_tree *t, int l, const OBlock *B, int d, int i, double *wm, double *wp) {
+    double ih2 = 1.0 / (t->lev[l].h[d] * t->lev[l].h[d]);
+    *wm = ih2;
+    *wp = ih2;
+    if (t->axisym && d == 0) {
+        double h = t->lev[l].h[0];
+        double r = t->lo[0] + (B->org[0] + i + 0.5) * h;
+        *wm = ih2 * (r - 0.5 * h) / r;
+        *wp = ih2 * (r + 0.5 * h) / r;
+    }
+}
+
 static double apply_L(const og_tree *t, int l, const OBlock *B, int i, int j, int k) {
     const double *v = B->fld[F_V];
     int c[3] = {i, j, k};
@@ -522,12 +544,13 @@ static double apply_L(const og_tree *t, int l, const OBlock *B, int i, int j, in
         cm[d] -= 1;
         cp[d] += 1;
         int pm = pidx3(t, l, cm), pp = pidx3(t, l, cp);
-        double ih2 = 1.0 / (t->lev[l].h[d] * t->lev[l].h[d]);
+        double wm, wp;
+        face_weights(t, l, B, d, i, &wm, &wp);
         if (!t->var_eps) {
-            sum += ih2 * (v[pm] - 2.0 * v[p] + v[pp]);
+            sum += wm * (v[pm] - v[p]) + wp * (v[pp] - v[p]);
         } else {
             const double *e = B->fld[F_EPS];
-            sum += ih2 * (harmonic(e[p], e[pm]) * (v[pm] - v[p]) + harmonic(e[p], e[pp]) * (v[pp] - v[p]));
+            sum += wm * harmonic(e[p], e[pm]) * (v[pm] - v[p]) + wp * harmonic(e[p], e[pp]) * (v[pp] - v[p]);
         }
     }
     return sum - t->lambda * v[p];
@@ -547,16 +570,15 @@ static double gs_value(const og_tree *t, int l, const OBlock *B, int i, int j, i
         cm[d] -= 1;
         cp[d] += 1;
         int pm = pidx3(t, l, cm), pp = pidx3(t, l, cp);
-        double ih2 = 1.0 / (t->lev[l].h[d] * t->lev[l].h[d]);
-        if (!t->var_eps) {
-            num += ih2 * (v[pm] + v[pp]);
-            den += 2.0 * ih2;
-        } else {
+        double wm, wp;
+        face_weights(t, l, B, d, i, &wm, &wp);
+        if (t->var_eps) {
             const double *e = B->fld[F_EPS];
-            double wm = harmonic(e[p], e[pm]) * ih2, wp = harmonic(e[p], e[pp]) * ih2;
-            num += wm * v[pm] + wp * v[pp];
-            den += wm + wp;
+            wm *= harmonic(e[p], e[pm]);
+            wp *= harmonic(e[p], e[pp]);
         }
+        num += wm * v[pm] + wp * v[pp];
+        den += wm + wp;
     }
     return (num - B->fld[F_F][p]) / (den + t->lambda);
 }

@@ -45,6 +45,9 @@ enum { OG_SMOOTH_GSRB = 0, OG_SMOOTH_JACOBI = 1 };
 void og_set_smoother(og_tree *t, int kind, double omega);
 /* Helmholtz term (Sec. 2.1 equation list): L phi = div(eps grad phi) - lambda phi. */
 void og_set_lambda(og_tree *t, double lambda);
+/* 2D axisymmetric operator (x = r >= 0, y = z): (1/r) d/dr (r dphi/dr) + d2phi/dz2
+ * (with eps and lambda as above).  Returns -1 unless dim = 2 and lo[0] >= 0. */
+int og_set_axisymmetric(og_tree *t, int on);
 
 /* Structure queries. */
 int og_num_levels(const og_tree *t);
