@@ -107,6 +107,15 @@ typedef struct {
                                  paper) */
     double helmholtz_lambda;  /* lambda >= 0 of the Helmholtz form div(eps grad phi) -
                                  lambda phi = f (Sec. 2.1 equation list); default 0 */
+    int32_t axisymmetric;     /* 1: 2D cylindrical form of Sec. 2.1, x is the radius r >= 0
+                                 and y the axis z: (1/r) d/dr (eps r dphi/dr) + d/dz (eps
+                                 dphi/dz) in finite-volume form, i.e. the two r-face
+                                 weights of a cell are scaled by (face radius) / (cell-centre
+                                 radius).  Needs dim 2, lo[0] >= 0 and non-periodic x faces
+                                 in every domain (the face at r = 0 gets weight 0, so its
+                                 boundary condition has no effect there).  Restriction stays
+                                 the plain mean and norms keep Cartesian cell volumes.
+                                 mg_face_gradient is not available.  Default 0. */
 } mg_params;
 
 /* Fills p with the paper's defaults (Sec. 2.4) and FP64 precision. */
@@ -114,7 +123,8 @@ int mg_default_params(mg_params *p);
 
 /* Builds the tree(s) on the host.  block_size must be 4, 8 or 16; every domain's
  * base_cells must be multiples of it.  max_refine_levels >= 0 limits refinement
- * above the base grid.  Returns MG_ERR_ARG for invalid input. */
+ * above the base grid.  Returns MG_ERR_ARG for invalid input (also for a domain that
+ * does not meet the requirements of params->axisymmetric when that is set). */
 int mg_tree_create(const mg_domain *domains, int n_domains, int block_size,
                    int max_refine_levels, mg_refine_fn refine, void *user_data,
                    const mg_params *params, mg_tree **out);

@@ -123,6 +123,7 @@ size_t plan(mg_tree *t, char *base) {
     size_t o_bck = L.take<int32_t>(6 * T.ndom), o_bcv = L.take<double>(6 * T.ndom), o_bc0 = L.take<double>(6 * T.ndom);
     size_t o_toff = L.take<int64_t>((size_t)T.ndom * MAXLEV);
     size_t o_ttop = L.take<int32_t>(T.ndom);
+    size_t o_lox = L.take<double>(T.ndom);
     std::vector<size_t> o_parl(T.nlev), o_cfl(T.nlev);
     for (int l = 0; l < T.nlev; l++) {
         o_parl[l] = L.take<int32_t>(T.parents_of_level[l].size());
@@ -157,6 +158,9 @@ size_t plan(mg_tree *t, char *base) {
         put(o_bc0, bc0.data(), bc0.size() * 8);
         put(o_toff, T.tail_off.data(), T.tail_off.size() * 8);
         put(o_ttop, T.tail_top.data(), T.tail_top.size() * 4);
+        std::vector<double> lox(T.ndom);
+        for (int i = 0; i < T.ndom; i++) lox[i] = T.doms[i].d.lo[0];
+        put(o_lox, lox.data(), lox.size() * 8);
         for (int l = 0; l < T.nlev; l++) {
             put(o_parl[l], T.parents_of_level[l].data(), T.parents_of_level[l].size() * 4);
             put(o_cfl[l], T.cf_of_level[l].data(), T.cf_of_level[l].size() * 4);
@@ -177,6 +181,8 @@ size_t plan(mg_tree *t, char *base) {
         tb.tail_off = (const int64_t *)P(o_toff);
         tb.tail_top = (const int32_t *)P(o_ttop);
         tb.lambda = t->prm.helmholtz_lambda;
+        tb.axi = t->prm.axisymmetric;
+        tb.lox = (const double *)P(o_lox);
         t->tb0 = tb;
         t->tb0.bcv = (const double *)P(o_bc0);
         t->d_parents.assign(T.nlev, nullptr);
@@ -755,6 +761,7 @@ int mg_default_params(mg_params *p) {
     p->smoother = MG_SMOOTH_GSRB;
     p->jacobi_weight = 2.0 / 3.0;
     p->helmholtz_lambda = 0.0;
+    p->axisymmetric = 0;
     return MG_OK;
 }
 
@@ -770,9 +777,19 @@ int mg_tree_create(const mg_domain *domains, int n_domains, int block_size, int 
         (p.precision != MG_FP64 && p.precision != MG_MIXED) || p.ir_vcycles < 1 || (p.graphs != 0 && p.graphs != 1) ||
         p.krylov < 0 || p.krylov > 64 || (p.krylov > 0 && p.precision != MG_MIXED) ||
         (p.smoother != MG_SMOOTH_GSRB && p.smoother != MG_SMOOTH_JACOBI) ||
-        !(p.jacobi_weight > 0.0 && p.jacobi_weight <= 1.0) || !(p.helmholtz_lambda >= 0.0)) {
+        !(p.jacobi_weight > 0.0 && p.jacobi_weight <= 1.0) || !(p.helmholtz_lambda >= 0.0) ||
+        (p.axisymmetric != 0 && p.axisymmetric != 1)) {
         delete t;
         return MG_ERR_ARG;
+    }
+    if (p.axisymmetric && domains) {
+        // the cylindrical form: x is a radius (>= 0) and has no periodic copy
+        for (int i = 0; i < n_domains; i++)
+            if (domains[i].dim != 2 || !(domains[i].lo[0] >= 0.0) || domains[i].bc.kind[0] == MG_BC_PERIODIC ||
+                domains[i].bc.kind[1] == MG_BC_PERIODIC) {
+                delete t;
+                return MG_ERR_ARG;
+            }
     }
     std::string e = build_tree(t->T, domains, n_domains, block_size, max_refine_levels, refine, user_data);
     if (!e.empty()) {
@@ -1102,6 +1119,7 @@ int mg_face_gradient(mg_tree *t, const double *leaf_phi, const double *leaf_lamb
     if (rc) return rc;
     if (!leaf_phi || !leaf_lambda || !out) return MG_ERR_ARG;
     if (t->T.refined) return fail(t, MG_ERR_ARG, "face gradient needs a tree without refinement");
+    if (t->prm.axisymmetric) return fail(t, MG_ERR_ARG, "face gradient is Cartesian only (axisymmetric tree)");
     if (!var(t)) return fail(t, MG_ERR_STATE, "tree was created with variable_eps = 0");
     const double *phi = stage_in(t, leaf_phi, on_device, t->d_stage, &rc);
     if (rc) return rc;

@@ -35,6 +35,8 @@ struct DevTables {
     const int64_t *tail_off;  // [ndom][MAXLEV] offset of a tail level's padded array (cells)
     const int32_t *tail_top;  // [ndom] highest tail level run by the one-workgroup kernel
     double lambda;            // Helmholtz term: L phi = div(eps grad phi) - lambda phi
+    int axi;                  // 2D axisymmetric form (x = r): r-face factors on the x faces
+    const double *lox;        // [ndom] lower x bound (the radius of the domain's inner face)
 };
 
 // Tail levels with more cells than this (per domain) run as multi-workgroup launches;

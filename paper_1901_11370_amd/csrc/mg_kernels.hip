@@ -87,6 +87,20 @@ __device__ __forceinline__ T harm(T a, T b) {
     return T(2) * a * b / (a + b);
 }
 
+// Factors of the two x-face weights in the 2D axisymmetric form (x = r, finite volumes
+// of (1/r) d/dr (r dphi/dr)): face radius over cell-centre radius, for the cell with
+// global x index gi on a level of x spacing h (1 and 1 otherwise).
+template <int D>
+__device__ __forceinline__ void axi_factors(const DevTables &tb, int dm, double h, int gi, double &fm, double &fp) {
+    fm = 1.0;
+    fp = 1.0;
+    if (D == 2 && tb.axi) {
+        const double r = tb.lox[dm] + (gi + 0.5) * h;
+        fm = (r - 0.5 * h) / r;
+        fp = (r + 0.5 * h) / r;
+    }
+}
+
 // ------------------------------------------------------- LDS staging helper
 // Copies NRUN runs of LEN elements (run r at src + r * STRIDE) to dst + r * LEN with
 // the widest aligned vector loads, all of a thread's loads issued before any store,
@@ -127,6 +141,8 @@ struct Stager {
 struct Spacing {
     double ih2[3];
     double lam;   // Helmholtz term
+    double hx;    // x spacing (axisymmetric factors, see axi_factors)
+    int axi;
 };
 
 __device__ __forceinline__ Spacing spacing(const DevTables &tb, int dm, int lev) {
@@ -134,6 +150,8 @@ __device__ __forceinline__ Spacing spacing(const DevTables &tb, int dm, int lev)
     Spacing s;
     for (int a = 0; a < 3; a++) s.ih2[a] = 1.0 / (h[a] * h[a]);
     s.lam = tb.lambda;
+    s.axi = tb.axi;
+    s.hx = h[0];
     return s;
 }
 
@@ -142,7 +160,7 @@ template <typename T, int D, int BS, bool VAR>
 struct Stencil {
     T nb[6], w[6], vc, lam;
     __device__ __forceinline__ void load(const Plane<T> &P, int64_t b, int i, int j, int k,
-                                         const Spacing &s, bool need_center) {
+                                         const Spacing &s, bool need_center, double rx = 0.0) {
         nb[0] = ld<D, BS>(P.v, P.vg, b, i - 1, j, k);
         nb[1] = ld<D, BS>(P.v, P.vg, b, i + 1, j, k);
         nb[2] = ld<D, BS>(P.v, P.vg, b, i, j - 1, k);
@@ -167,6 +185,10 @@ struct Stencil {
                 en[5] = ld<D, BS>(P.eps, P.epsg, b, i, j, k + 1);
             }
             for (int f = 0; f < 2 * D; f++) w[f] = harm(e0, en[f]) * T(s.ih2[f / 2]);
+        }
+        if (D == 2 && s.axi) {   // rx: radius of this cell's centre
+            w[0] *= T((rx - 0.5 * s.hx) / rx);
+            w[1] *= T((rx + 0.5 * s.hx) / rx);
         }
     }
     __device__ __forceinline__ T Lv() const {
@@ -220,13 +242,14 @@ __device__ __forceinline__ void push_ghosts(T *__restrict__ vg, const DevTables 
 // with the first data loads instead of forming a chain of dependent round trips.
 template <int D>
 struct BlockCtx {
-    int dm;
+    int dm, orgx;
     int nbr[6];
     double h[3];
     int bck[6];
     double bcv[6];
     __device__ __forceinline__ void load(const DevTables &tb, int64_t b, int lev) {
         dm = tb.dom[b];
+        orgx = tb.org[3 * b];
 #pragma unroll
         for (int f = 0; f < 2 * D; f++) nbr[f] = tb.nbr[6 * b + f];
         const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
@@ -345,9 +368,18 @@ __global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev,
         }
         T num = T(0), den = T(tb.lambda);
         const T fval = fr[m];
+        double fm, fp;
+        axi_factors<D>(tb, cx.dm, cx.h[0], cx.orgx + i, fm, fp);
         if (!VAR) {
+            if (D == 2 && tb.axi) {
+                num += ih2[0] * (T(fm) * (gho[0] ? s_g[off[0]] : s_o[off[0]]) +
+                                 T(fp) * (gho[1] ? s_g[off[1]] : s_o[off[1]]));
 #pragma unroll
-            for (int f = 0; f < 2 * D; f++) num += ih2[f >> 1] * (gho[f] ? s_g[off[f]] : s_o[off[f]]);
+                for (int f = 2; f < 2 * D; f++) num += ih2[f >> 1] * (gho[f] ? s_g[off[f]] : s_o[off[f]]);
+            } else {
+#pragma unroll
+                for (int f = 0; f < 2 * D; f++) num += ih2[f >> 1] * (gho[f] ? s_g[off[f]] : s_o[off[f]]);
+            }
 #pragma unroll
             for (int a = 0; a < D; a++) den += T(2) * ih2[a];
         } else {
@@ -355,7 +387,9 @@ __global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev,
 #pragma unroll
             for (int f = 0; f < 2 * D; f++) {
                 const T en = gho[f] ? s_eg[off[f]] : s_eo[off[f]];
-                const T w = harm(e0, en) * ih2[f >> 1];
+                T w = harm(e0, en) * ih2[f >> 1];
+                if (f == 0) w *= T(fm);
+                if (f == 1) w *= T(fp);
                 num += w * (gho[f] ? s_g[off[f]] : s_o[off[f]]);
                 den += w;
             }
@@ -414,9 +448,17 @@ __global__ void __launch_bounds__(256) k_jacobi(Plane<T> P, T *__restrict__ dst,
             nb[5] = k < BS - 1 ? s_v[g::in(i, j, k + 1)] : s_v[g::NC + g::gh(5, i, j)];
         }
         T num = T(0), den = T(tb.lambda);
+        double fm, fp;
+        axi_factors<D>(tb, cx.dm, cx.h[0], cx.orgx + i, fm, fp);
         if (!VAR) {
+            // the axisymmetric x-face factors sum to 2: the diagonal is unchanged
+            const T nx0 = D == 2 && tb.axi ? T(fm) * nb[0] : nb[0], nx1 = D == 2 && tb.axi ? T(fp) * nb[1] : nb[1];
+            num += ih2[0] * nx0;
+            num += ih2[0] * nx1;
+            den += ih2[0];
+            den += ih2[0];
 #pragma unroll
-            for (int f = 0; f < 2 * D; f++) {
+            for (int f = 2; f < 2 * D; f++) {
                 num += ih2[f >> 1] * nb[f];
                 den += ih2[f >> 1];
             }
@@ -433,7 +475,9 @@ __global__ void __launch_bounds__(256) k_jacobi(Plane<T> P, T *__restrict__ dst,
             }
 #pragma unroll
             for (int f = 0; f < 2 * D; f++) {
-                const T w = harm(e0, en[f]) * ih2[f >> 1];
+                T w = harm(e0, en[f]) * ih2[f >> 1];
+                if (f == 0) w *= T(fm);
+                if (f == 1) w *= T(fp);
                 num += w * nb[f];
                 den += w;
             }
@@ -632,6 +676,12 @@ __global__ void __launch_bounds__(256) k_restrict(Plane<T> P, DevTables tb, int 
                     nb[5] = k < BS - 1 ? s_v[g::in(i, j, k + 1)] : s_v[g::NC + g::gh(5, i, j)];
                 }
                 T lv = T(0);
+                if (D == 2 && tb.axi) {   // axisymmetric x-face factors (see axi_factors)
+                    double fm, fp;
+                    axi_factors<D>(tb, dm, hh[0], ob[0] + i, fm, fp);
+                    nb[0] = vc + T(fm) * (nb[0] - vc);
+                    nb[1] = vc + T(fp) * (nb[1] - vc);
+                }
                 if (!VAR) {
 #pragma unroll
                     for (int f = 0; f < 2 * D; f++) lv += ih2[f >> 1] * (nb[f] - vc);
@@ -693,8 +743,9 @@ __global__ void __launch_bounds__(256) k_fas(Plane<T> P, DevTables tb, int lev, 
         const Spacing s = spacing(tb, dm, lev);
         int i, j, k;
         g::decode(t, i, j, k);
+        const double rx = D == 2 && tb.axi ? tb.lox[dm] + (tb.org[3 * b] + i + 0.5) * s.hx : 0.0;
         Stencil<T, D, BS, VAR> st;
-        st.load(P, b, i, j, k, s, true);
+        st.load(P, b, i, j, k, s, true, rx);
         const T fv = P.f[b * g::NC + t];
         if (!((mask >> dm) & 1)) return;
         P.vold[b * g::NC + t] = st.vc;
@@ -826,6 +877,8 @@ struct TailLev {
     double h[3], ih2[3];
     double inv_den;    // 1 / (2 sum ih2 + lambda): the constant-coefficient diagonal
     double lam;        // Helmholtz term
+    double rlo;        // axisymmetric form: radius of the domain's inner x face
+    int axi;
 };
 struct TailBC {
     int kind[6];
@@ -946,6 +999,11 @@ struct Tail {
             nb[f] = tv[o + d];
             w[f] = T(g.ih2[f >> 1]);
             if (VAR) w[f] *= harm(teps[o], teps[o + d]);
+        }
+        if (D == 2 && g.axi) {   // axisymmetric x-face factors (see axi_factors)
+            const double r = g.rlo + (i + 0.5) * g.h[0];
+            w[0] *= T((r - 0.5 * g.h[0]) / r);
+            w[1] *= T((r + 0.5 * g.h[0]) / r);
         }
     }
     __device__ __forceinline__ T Lv(const TailLev &g, int i, int j, int k) const {
@@ -1296,6 +1354,8 @@ __device__ __forceinline__ void tail_setup(const DevTables &tb, int dm, int nlev
             g.ih2[a] = 0.0;
         }
         g.lam = tb.lambda;
+        g.axi = tb.axi;
+        g.rlo = tb.axi ? tb.lox[dm] : 0.0;
         g.inv_den = 1.0 / (2.0 * (g.ih2[0] + g.ih2[1] + g.ih2[2]) + g.lam);
         lv[l] = g;
     }
@@ -1400,7 +1460,8 @@ __device__ __forceinline__ int64_t uidx(const UGrid &g, int i, int j, int k, int
 }
 
 template <typename T, int D, bool VAR>
-__device__ __forceinline__ void ustencil(const Plane<T> &P, const UGrid &g, int i, int j, int k, T *w, T *nb) {
+__device__ __forceinline__ void ustencil(const Plane<T> &P, const DevTables &tb, const UGrid &g, int i, int j, int k,
+                                         T *w, T *nb) {
     nb[0] = P.tv[uidx(g, i - 1, j, k, D)];
     nb[1] = P.tv[uidx(g, i + 1, j, k, D)];
     nb[2] = P.tv[uidx(g, i, j - 1, k, D)];
@@ -1414,6 +1475,12 @@ __device__ __forceinline__ void ustencil(const Plane<T> &P, const UGrid &g, int 
         const T e0 = P.teps[uidx(g, i, j, k, D)];
         const int o[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k}, {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
         for (int f = 0; f < 2 * D; f++) w[f] *= harm(e0, P.teps[uidx(g, o[f][0], o[f][1], o[f][2], D)]);
+    }
+    if (D == 2 && tb.axi) {
+        double fm, fp;
+        axi_factors<D>(tb, g.dm, g.h[0], i, fm, fp);
+        w[0] *= T(fm);
+        w[1] *= T(fp);
     }
 }
 
@@ -1452,7 +1519,7 @@ __global__ void __launch_bounds__(256) k_ugsrb(Plane<T> P, DevTables tb, UGrid g
     const int j = row % g.n[1], k = D == 3 ? row / g.n[1] : 0;
     const int i = 2 * pos + ((j + k + colour) & 1);
     T w[6], nb[6];
-    ustencil<T, D, VAR>(P, g, i, j, k, w, nb);
+    ustencil<T, D, VAR>(P, tb, g, i, j, k, w, nb);
     T num = T(0), den = T(tb.lambda);
     for (int f = 0; f < 2 * D; f++) {
         num += w[f] * nb[f];
@@ -1478,7 +1545,7 @@ __global__ void __launch_bounds__(256) k_ujacobi(Plane<T> P, const T *src, T *ds
     S.tv = const_cast<T *>(src);
     Q.tv = dst;
     T w[6], nb[6];
-    ustencil<T, D, VAR>(S, g, i, j, k, w, nb);
+    ustencil<T, D, VAR>(S, tb, g, i, j, k, w, nb);
     T num = T(0), den = T(tb.lambda);
     for (int f = 0; f < 2 * D; f++) {
         num += w[f] * nb[f];
@@ -1515,7 +1582,7 @@ __global__ void __launch_bounds__(256) k_ufas(Plane<T> P, DevTables tb, UGrid g)
     const int j = r % (g.n[1] + 2) - 1, k = D == 3 ? r / (g.n[1] + 2) - 1 : 0;
     if (i < 0 || i >= g.n[0] || j < 0 || j >= g.n[1] || (D == 3 && (k < 0 || k >= g.n[2]))) return;
     T w[6], nb[6];
-    ustencil<T, D, VAR>(P, g, i, j, k, w, nb);
+    ustencil<T, D, VAR>(P, tb, g, i, j, k, w, nb);
     const T vc = P.tv[g.off + q];
     T lv = -T(tb.lambda) * vc;
     for (int f = 0; f < 2 * D; f++) lv += w[f] * (nb[f] - vc);
@@ -1534,7 +1601,7 @@ __global__ void __launch_bounds__(256) k_urestrict(Plane<T> P, DevTables tb, UGr
     for (int c = 0; c < (1 << D); c++) {
         const int i = 2 * I + (c & 1), j = 2 * J + ((c >> 1) & 1), k = D == 3 ? 2 * K + (c >> 2) : 0;
         T w[6], nb[6];
-        ustencil<T, D, VAR>(P, g, i, j, k, w, nb);
+        ustencil<T, D, VAR>(P, tb, g, i, j, k, w, nb);
         const int64_t o = uidx(g, i, j, k, D);
         const T vc = P.tv[o];
         T lv = -T(tb.lambda) * vc;
@@ -1659,6 +1726,7 @@ __global__ void __launch_bounds__(256) k_norm(Plane<double> P, DevTables tb, dou
     }
     const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
     const double h0 = hh[0], h1 = hh[1], h2 = hh[2];
+    const int orgx = tb.org[3 * b];
     st_v.store(s_v);
     st_g.store(s_v + g::NC);
     __syncthreads();
@@ -1683,6 +1751,12 @@ __global__ void __launch_bounds__(256) k_norm(Plane<double> P, DevTables tb, dou
         if (D == 3) {
             nb[4] = k > 0 ? s_v[g::in(i, j, k - 1)] : s_v[g::NC + g::gh(4, i, j)];
             nb[5] = k < BS - 1 ? s_v[g::in(i, j, k + 1)] : s_v[g::NC + g::gh(5, i, j)];
+        }
+        if (D == 2 && tb.axi) {   // axisymmetric x-face factors (see axi_factors)
+            double fm, fp;
+            axi_factors<D>(tb, dm, h0, orgx + i, fm, fp);
+            nb[0] = vc + fm * (nb[0] - vc);
+            nb[1] = vc + fp * (nb[1] - vc);
         }
         double lv = 0.0;
         if (!VAR) {
@@ -1983,7 +2057,7 @@ constexpr int kTailLds = 150 * 1024;
 
 template <typename K>
 static void allow_lds(K kernel) {
-    hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, kTailLds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, kTailLds);
 }
 
 void prepare_kernels() {

@@ -50,7 +50,7 @@ class mg_params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("variable_eps", ctypes.c_int32),
                 ("ir_first_fmg", ctypes.c_int32), ("ir_vcycles", ctypes.c_int32), ("graphs", ctypes.c_int32),
                 ("krylov", ctypes.c_int32), ("smoother", ctypes.c_int32), ("jacobi_weight", ctypes.c_double),
-                ("helmholtz_lambda", ctypes.c_double)]
+                ("helmholtz_lambda", ctypes.c_double), ("axisymmetric", ctypes.c_int32)]
 
 
 mg_refine_fn = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,

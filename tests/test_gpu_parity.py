@@ -26,6 +26,8 @@ def _run(w, script, tol=TOL, remove_mean=False, **params):
             o.set_params(n_down=params.get("n_down", 2), n_up=params.get("n_up", 2))
         if "helmholtz_lambda" in params:
             o.set_lambda(params["helmholtz_lambda"])
+        if params.get("axisymmetric", 0):
+            o.set_axisymmetric()
     f, e = inputs(w, t)
     if w.variable_eps:
         t.set_eps(np.concatenate(e))
@@ -274,17 +276,73 @@ def test_helmholtz(case):
         _mixed_vs_reference_l(W.config3(nested=False, base=32), 1e-8, 250.0)
 
 
-def _mixed_vs_reference_l(w, tol, lam):
+def _mixed_vs_reference_l(w, tol, lam, axisymmetric=0):
     import torch
-    t = gpu_tree(w, precision=1, helmholtz_lambda=lam)
+    t = gpu_tree(w, precision=1, helmholtz_lambda=lam, axisymmetric=axisymmetric)
     refs = oracle_trees(w)
     f, e = inputs(w, t)
     t.set_rhs(torch.from_numpy(np.concatenate(f)).cuda())
     cycles, rc = t.solve(rel_tol=1e-10, max_cycles=40)
     for o, fi in zip(refs, f):
         o.set_lambda(lam)
+        if axisymmetric:
+            o.set_axisymmetric()
         o.set_rhs(fi)
         o.solve(rel_tol=1e-12, max_cycles=60)
     errs = [rel_err(p, o.get_phi()) for p, o in zip(split(t, t.get_phi()), refs)]
     print("mixed helmholtz", cycles, errs, flush=True)
     assert rc == 0 and max(errs) <= tol
+
+
+# ------------------------------------------------------- 2D axisymmetric form
+def _axi_domain(n=(64, 128), lo=(0.0, -1.0), hi=(1.0, 1.0), kinds=None, values=None):
+    # x is the radius: the face at r = 0 has weight 0, so its kind does not matter
+    kinds = kinds or [W.NEUMANN, W.DIRICHLET, W.DIRICHLET, W.DIRICHLET]
+    values = values or [0.0, 0.5, -0.25, 1.0]
+    return W.Domain(2, list(n), list(lo), list(hi), kinds, values)
+
+
+def _axi_workload(name, doms, bs=16, **kw):
+    srcs = [W.Gaussians(np.array([[d.lo[0] + 0.3 * (d.hi[0] - d.lo[0]), 0.5 * (d.lo[1] + d.hi[1])]]),
+                        np.array([4.0]), np.array([0.12])) for d in doms]
+    return W.Workload(name, doms, bs=bs, rhs=lambda i, lay: srcs[i](W.cell_centres(lay, doms[i])), **kw)
+
+
+@pytest.mark.parametrize("case", ["axis_dirichlet", "annulus_neumann", "amr_axis", "var_jacobi", "forest_helmholtz",
+                                  "large_coarse", "mixed"])
+def test_axisymmetric(case):
+    if case == "axis_dirichlet":
+        _run(_axi_workload("axi", [_axi_domain()]), "fvvnv", axisymmetric=1)
+    elif case == "annulus_neumann":
+        # r in [0.5, 1.5], periodic in z, a Neumann flux at the outer radius
+        d = _axi_domain((64, 64), (0.5, 0.0), (1.5, 1.0), [W.DIRICHLET, W.NEUMANN, W.PERIODIC, W.PERIODIC],
+                        [1.0, -0.5, 0.0, 0.0])
+        _run(_axi_workload("axiann", [d]), "vfvn", axisymmetric=1)
+    elif case == "amr_axis":
+        # refinement around a source on the axis: coarse-fine faces next to r = 0
+        d = _axi_domain((32, 64))
+        g = W.Gaussians(np.array([[0.05, 0.1]]), np.array([6.0]), np.array([0.08]))
+
+        def refine(dom, level, origin, bs, dm=d):
+            h = (dm.hi[0] - dm.lo[0]) / (dm.base_cells[0] << level)
+            cx = dm.lo[0] + (origin[0] + bs / 2) * h
+            cy = dm.lo[1] + (origin[1] + bs / 2) * h
+            return level < 2 and (cx - 0.05) ** 2 + (cy - 0.1) ** 2 < (0.3 / (level + 1)) ** 2
+
+        w = W.Workload("axiamr", [d], bs=8, max_refine=2, refine=refine,
+                       rhs=lambda i, lay: g(W.cell_centres(lay, d)))
+        _run(w, "fvvnv", axisymmetric=1)
+    elif case == "var_jacobi":
+        d = _axi_domain((64, 64), (0.0, 0.0), (1.0, 1.0))
+        w = _axi_workload("axivar", [d], variable_eps=True, eps=lambda i, lay: _smooth_eps(d, lay))
+        _run(w, "vfv", axisymmetric=1, smoother=1)
+        _run(w, "fvv", axisymmetric=1)
+    elif case == "forest_helmholtz":
+        doms = [_axi_domain((32, 64)), _axi_domain((48, 48), (2.0, 0.0), (3.0, 1.0))]
+        _run(_axi_workload("axiforest", doms), "fvvn", axisymmetric=1, helmholtz_lambda=30.0)
+    elif case == "large_coarse":
+        # 768^2: coarse grids above 4096 cells run as grid-wide launches
+        d = _axi_domain((768, 768), (0.0, 0.0), (1.0, 1.0))
+        _run(_axi_workload("axibig", [d]), "fvv", axisymmetric=1)
+    else:
+        _mixed_vs_reference_l(_axi_workload("aximix", [_axi_domain()]), 1e-8, 0.0, axisymmetric=1)

@@ -82,3 +82,15 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(mg.MGError):
         mg.Tree([d], bs=16, bind=False, params=mg.default_params(precision=mg.MG_MIXED, krylov=65))
     mg.Tree([d], bs=16, bind=False, params=mg.default_params(precision=mg.MG_MIXED, krylov=64))
+    # the axisymmetric form: 2D only, radius lo[0] >= 0, no periodic copy across r
+    axi = mg.default_params(axisymmetric=1)
+    with pytest.raises(mg.MGError):
+        mg.Tree([d], bs=16, bind=False, params=axi)
+    with pytest.raises(mg.MGError):
+        mg.Tree([mg.Domain(2, (32, 32), (-0.5, 0), (0.5, 1), [0] * 4)], bs=16, bind=False, params=axi)
+    with pytest.raises(mg.MGError):
+        mg.Tree([mg.Domain(2, (32, 32), (0, 0), (1, 1), [2, 2, 0, 0])], bs=16, bind=False, params=axi)
+    with pytest.raises(mg.MGError):
+        mg.Tree([mg.Domain(2, (32, 32), (0, 0), (1, 1), [0] * 4)], bs=16, bind=False,
+                params=mg.default_params(axisymmetric=2))
+    mg.Tree([mg.Domain(2, (32, 32), (0, 0), (1, 1), [1, 0, 2, 2])], bs=16, bind=False, params=axi)
