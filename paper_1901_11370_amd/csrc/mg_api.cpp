@@ -572,7 +572,10 @@ int worst(const mg_tree *t, const std::vector<double> &n, double *mx, double *l2
 // One step of iterative refinement: r = f - L phi in FP64 (also the norm), then the
 // FP32 correction solve L e = r with zero initial guess and homogeneous boundary
 // values, then phi += e on the leaves.
-void ir_enqueue(mg_tree *t, bool use_fmg) {
+// One refinement step's correction: FP32 cycle(s) on L e = r (r in the FP32 right-hand
+// side, e from zero), then phi += e unless the caller fuses that with the next residual
+// (enq_add_residual).
+void ir_enqueue(mg_tree *t, bool use_fmg, bool defer_add = false) {
     Driver<float> D = d32(t);
     const Plane<float> &P = t->P32;
     K<float>::zero(D.L, P.v, (size_t)(t->nb * t->nc));
@@ -583,8 +586,24 @@ void ir_enqueue(mg_tree *t, bool use_fmg) {
     } else {
         for (int c = 0; c < std::max(1, t->prm.ir_vcycles); c++) D.vcycle(t->T.nlev - 1, all_mask(t));
     }
+    if (defer_add) return;
     Launch L64 = launch(t, t->homog);
     launch_add_leaf(L64, t->P64.v, t->P64.vg, P.v, (int)t->nleafblk);
+}
+
+// phi += e (the FP32 correction left by ir_enqueue(..., true)), then the residual as
+// enq_residual: one fused launch on trees without refinement.
+void enq_add_residual(mg_tree *t, bool write_r32, bool copy_out) {
+    if (t->T.refined) {
+        launch_add_leaf(launch(t, t->homog), t->P64.v, t->P64.vg, t->P32.v, (int)t->nleafblk);
+        enq_residual(t, write_r32, copy_out);
+        return;
+    }
+    Driver<double> D = d64(t);
+    launch_add_norm64(D.L, t->P64, t->P32.v, t->P32.vg, (int)t->nleafblk, var(t), write_r32 ? t->P32.f : nullptr);
+    launch_reduce_norms(D.L);
+    if (copy_out)
+        (void)hipMemcpyAsync(t->h_norms, t->d_domnorms, 4 * (size_t)t->T.ndom * 8, hipMemcpyDeviceToHost, t->stream);
 }
 
 // ---- FGMRES refinement (mixed mode, krylov = m)
@@ -1090,8 +1109,8 @@ int mg_solve(mg_tree *t, double rel_tol, int max_cycles, int use_fmg_first, int 
             if (rel <= rel_tol || cycles >= max_cycles) break;
             const bool f = cycles == 0 && use_fmg_first && t->prm.ir_first_fmg;
             if ((rc = run_seq(t, f ? G_IRFMG_NORM : G_IRV_NORM, [&] {
-                     ir_enqueue(t, f);
-                     enq_residual(t, true, true);
+                     ir_enqueue(t, f, true);
+                     enq_add_residual(t, true, true);
                  })))
                 return rc;
             cycles++;

@@ -129,6 +129,9 @@ void prepare_kernels();
 // FP64 composite residual over the leaf blocks; optionally writes r (cast) into rout.
 void launch_norm64(const Launch &L, const Plane<double> &P, int nleafblk, bool var, float *rout32,
                    double *rout64);
+// v += e on the leaf blocks, then the residual as launch_norm64 (trees without refinement).
+void launch_add_norm64(const Launch &L, const Plane<double> &P, const float *e, const float *eg, int nleafblk,
+                       bool var, float *rout32);
 void launch_reduce_norms(const Launch &L);
 void launch_add_leaf(const Launch &L, double *v64, double *vg64, const float *v32, int nleafblk);
 // Krylov support on leaf vectors (rank-major: x[rank * cells_per_block + t]).

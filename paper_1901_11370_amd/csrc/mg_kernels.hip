@@ -1702,33 +1702,99 @@ __device__ __forceinline__ void block_reduce4(double &mr, double &sr, double &mf
 // blocks of an output field (the right-hand side of an FP32 correction solve) or into
 // a leaf vector (rank-major, see the Krylov section).  Without f (P.f null) the
 // vector receives L v instead: the operator applied to v.
-// One workgroup per leaf block, v with its ghosts staged in LDS.
-template <int D, int BS, bool VAR>
-__global__ void __launch_bounds__(256) k_norm(Plane<double> P, DevTables tb, double *partials,
-                                              float *rout32, double *rout64) {
+// One workgroup per leaf block, v with its ghosts staged in LDS (16-byte loads, all
+// issued before the first LDS store).
+// ADD: the block first takes the FP32 correction, v += e, and the residual is that of
+// the corrected v.  Same-level ghosts become ghost(v) + ghost(e) (both hold the
+// neighbour's values, so the sum is the neighbour's new value, rounded the same way),
+// physical-boundary ghosts are recomputed from the new boundary cells, and v and the
+// block's own ghosts are written back.  Only for trees without refinement: there are
+// no coarse-fine ghosts, and no block writes another block's memory.
+template <int D, int BS, bool VAR, bool ADD, int TPB>
+__global__ void __launch_bounds__(TPB) k_resid(Plane<double> P, DevTables tb, const float *__restrict__ e,
+                                               const float *__restrict__ eg, double *partials, float *rout32,
+                                               double *rout64) {
     using g = G<D, BS>;
-    constexpr int TPB = 256;
+    constexpr int NP = g::NC / 2, NGP = g::NG / 2;   // 16-byte pairs
+    constexpr int IP = (NP + TPB - 1) / TPB, IG = (NGP + TPB - 1) / TPB;
     constexpr int IT = (g::NC + TPB - 1) / TPB;
     __shared__ __align__(16) double s_v[g::NC + g::NG];
     const int rank = blockIdx.x;
     const int64_t b = tb.leaf_blk[rank];
-    const int dm = tb.dom[b], lev = tb.lev[b];
     const int tid = threadIdx.x;
-    Stager<double, 1, g::NC, 0, TPB> st_v;
-    Stager<double, 1, g::NG, 0, TPB> st_g;
-    st_v.load(P.v + b * g::NC);
-    st_g.load(P.vg + b * g::NG);
+    double2 vr[IP], gr[IG];
+    float2 er[ADD ? IP : 1], egr[ADD ? IG : 1];
+#pragma unroll
+    for (int m = 0; m < IP; m++) {
+        int p = tid + m * TPB;
+        if (NP % TPB != 0) p = p < NP ? p : NP - 1;
+        vr[m] = reinterpret_cast<const double2 *>(P.v + b * g::NC)[p];
+        if (ADD) er[m] = reinterpret_cast<const float2 *>(e + b * g::NC)[p];
+    }
+#pragma unroll
+    for (int m = 0; m < IG; m++) {
+        int p = tid + m * TPB;
+        if (NGP % TPB != 0) p = p < NGP ? p : NGP - 1;
+        gr[m] = reinterpret_cast<const double2 *>(P.vg + b * g::NG)[p];
+        if (ADD) egr[m] = reinterpret_cast<const float2 *>(eg + b * g::NG)[p];
+    }
     double fr[IT];
 #pragma unroll
     for (int m = 0; m < IT; m++) {
         const int t = tid + m * TPB;
         fr[m] = P.f ? P.f[b * g::NC + (g::NC % TPB == 0 || t < g::NC ? t : 0)] : 0.0;
     }
-    const double *hh = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
-    const double h0 = hh[0], h1 = hh[1], h2 = hh[2];
-    const int orgx = tb.org[3 * b];
-    st_v.store(s_v);
-    st_g.store(s_v + g::NC);
+    BlockCtx<D> cx;
+    cx.load(tb, b, tb.lev[b]);
+    const int dm = cx.dm;
+    const double h0 = cx.h[0], h1 = cx.h[1], h2 = D == 3 ? cx.h[2] : 1.0;
+    unsigned same = 0;   // faces with a same-level neighbour (bit f); constant indices only
+#pragma unroll
+    for (int f = 0; f < 2 * D; f++) same |= (cx.nbr[f] >= 0 ? 1u : 0u) << f;
+#pragma unroll
+    for (int m = 0; m < IP; m++) {
+        const int p = tid + m * TPB;
+        if (NP % TPB != 0 && p >= NP) break;
+        double2 nv = vr[m];
+        if (ADD) {
+            nv.x += (double)er[m].x;
+            nv.y += (double)er[m].y;
+            reinterpret_cast<double2 *>(P.v + b * g::NC)[p] = nv;
+        }
+        reinterpret_cast<double2 *>(s_v)[p] = nv;
+    }
+#pragma unroll
+    for (int m = 0; m < IG; m++) {
+        const int p = tid + m * TPB;
+        if (NGP % TPB != 0 && p >= NGP) break;
+        double2 ng = gr[m];
+        if (ADD) {
+            if (!((same >> (2 * p / g::NF)) & 1u)) continue;   // physical face: below
+            ng.x += (double)egr[m].x;
+            ng.y += (double)egr[m].y;
+            reinterpret_cast<double2 *>(P.vg + b * g::NG)[p] = ng;
+        }
+        reinterpret_cast<double2 *>(s_v + g::NC)[p] = ng;
+    }
+    if (ADD) {
+        // physical-boundary ghosts from the corrected boundary cells
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < 2 * D; f++) {
+            if (cx.nbr[f] != -1) continue;
+            const int a = f >> 1, side = f & 1, c = side ? BS - 1 : 0;
+            for (int r = tid; r < g::NF; r += TPB) {
+                // invert g::gh: colour half, then tangential coordinates (a1, a2)
+                const int par = r / (g::NF / 2), rr = r % (g::NF / 2);
+                const int a2 = D == 3 ? rr / g::RH : 0;
+                const int a1 = 2 * (rr % g::RH) + ((par + a2 + (side ^ 1)) & 1);
+                const int i = a == 0 ? c : a1, j = a == 1 ? c : (a == 0 ? a1 : a2), k = a == 2 ? c : a2;
+                const double gv = bc_ghost<double>(cx.bck[f], cx.bcv[f], cx.h[a], side, s_v[g::in(i, j, k)]);
+                s_v[g::NC + f * g::NF + r] = gv;
+                P.vg[b * g::NG + f * g::NF + r] = gv;
+            }
+        }
+    }
     __syncthreads();
     double ih2[3];
     ih2[0] = 1.0 / (h0 * h0);
@@ -1754,7 +1820,7 @@ __global__ void __launch_bounds__(256) k_norm(Plane<double> P, DevTables tb, dou
         }
         if (D == 2 && tb.axi) {   // axisymmetric x-face factors (see axi_factors)
             double fm, fp;
-            axi_factors<D>(tb, dm, h0, orgx + i, fm, fp);
+            axi_factors<D>(tb, dm, h0, cx.orgx + i, fm, fp);
             nb[0] = vc + fm * (nb[0] - vc);
             nb[1] = vc + fp * (nb[1] - vc);
         }
@@ -2212,12 +2278,35 @@ void K<T>::gather(const Launch &L, const T *src, double *dst, int nleafblk) {
 template struct K<double>;
 template struct K<float>;
 
+// Threads per workgroup of the residual kernels.
+template <int D, int BS>
+constexpr int resid_tpb() { return 256; }
+
 void launch_norm64(const Launch &L, const Plane<double> &P, int nleafblk, bool var, float *rout32,
                    double *rout64) {
     if (nleafblk <= 0) return;
     DISPATCH_DB(L, {
-        if (var) k_norm<D, BS, true><<<nleafblk, 256, 0, L.stream>>>(P, L.tb, L.partials, rout32, rout64);
-        else k_norm<D, BS, false><<<nleafblk, 256, 0, L.stream>>>(P, L.tb, L.partials, rout32, rout64);
+        constexpr int TPB = resid_tpb<D, BS>();
+        if (var)
+            k_resid<D, BS, true, false, TPB><<<nleafblk, TPB, 0, L.stream>>>(P, L.tb, nullptr, nullptr, L.partials,
+                                                                             rout32, rout64);
+        else
+            k_resid<D, BS, false, false, TPB><<<nleafblk, TPB, 0, L.stream>>>(P, L.tb, nullptr, nullptr, L.partials,
+                                                                              rout32, rout64);
+    });
+}
+
+void launch_add_norm64(const Launch &L, const Plane<double> &P, const float *e, const float *eg, int nleafblk,
+                       bool var, float *rout32) {
+    if (nleafblk <= 0) return;
+    DISPATCH_DB(L, {
+        constexpr int TPB = resid_tpb<D, BS>();
+        if (var)
+            k_resid<D, BS, true, true, TPB><<<nleafblk, TPB, 0, L.stream>>>(P, L.tb, e, eg, L.partials, rout32,
+                                                                            nullptr);
+        else
+            k_resid<D, BS, false, true, TPB><<<nleafblk, TPB, 0, L.stream>>>(P, L.tb, e, eg, L.partials, rout32,
+                                                                             nullptr);
     });
 }
 

@@ -196,6 +196,18 @@ def test_mixed_precision_amr():
     _mixed_vs_reference(W.config3(nested=False, base=32), 1e-8)
 
 
+@pytest.mark.parametrize("bs", [8, 16])
+def test_mixed_precision_uniform_mixed_bc(bs):
+    # without refinement the correction and the next residual run as one launch, which
+    # rebuilds the Neumann and Dirichlet ghosts from the corrected boundary cells
+    dom = W.Domain(3, [32, 32, 48], [0, 0, 0], [1, 2, 1.5], [W.NEUMANN, W.DIRICHLET, W.PERIODIC, W.PERIODIC,
+                                                             W.DIRICHLET, W.NEUMANN],
+                   [0.3, -0.2, 0.0, 0.0, 1.0, 0.5])
+    g = W.Gaussians(np.array([[0.5, 1.0, 0.5]]), np.array([3.0]), np.array([0.2]))
+    w = W.Workload("mixbcmix", [dom], bs=bs, rhs=lambda i, lay: g(W.cell_centres(lay, dom)))
+    _mixed_vs_reference(w, 1e-8)
+
+
 def test_fp64_solve_reaches_tolerance_and_reference_agrees():
     w = W.config2(n=64)
     t = gpu_tree(w)
