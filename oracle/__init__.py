@@ -121,6 +121,7 @@ class OracleTree:
         if not self._h:
             raise ValueError("invalid tree arguments")
         self.lo, self.hi, self.base = lo, hi, base
+        self.bc_kind, self.bc_value = bc_kind, bc_value
         self.n_leaf = int(L.og_num_leaf_cells(self._h))
 
     def __del__(self):
