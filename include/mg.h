@@ -197,6 +197,27 @@ int mg_solve_stats(const mg_tree *t, int max_records, double *rel_residual, doub
 int mg_face_gradient(mg_tree *t, const double *leaf_phi, const double *leaf_lambda,
                      double *leaf_dJ_deps, int on_device);
 
+/* Elliptic divergence cleaning (Sec. 4.1, eq. poisson-divb and poisson-divb-cleaning):
+ * a cell-centred field B is projected with B <- B - grad phi, where lap phi = div B.
+ * leaf_B holds dim components, each a leaf array ([dim][n_leaf], component-major).
+ * Trees without refinement, with eps = 1, lambda = 0 and the Cartesian form only
+ * (MG_ERR_ARG otherwise).  The call sequence is mg_divb_rhs, a solve (mg_solve,
+ * mg_fmg, mg_vcycle; phi from mg_set_phi or zero), mg_divb_project.
+ *
+ * mg_divb_rhs sets f = div B, each derivative by second-order (order 2, eq.
+ * divb-central-diff) or fourth-order (order 4, eq. divb-4th-order) central
+ * differences; across a same-level (or periodic) face the neighbour block's cells are
+ * used, outside a physical face B repeats the boundary cell (both layers).  With a
+ * fully periodic domain the solve subtracts the mean of f on the coarsest grid.
+ *
+ * mg_divb_project sets B_d -= d phi / d x_d by second-order central differences of
+ * the current phi and its boundary ghosts, in place; with leaf_e (may be NULL) the
+ * energy density is updated as e += (|B_new|^2 - |B_old|^2) / 2 (eq.
+ * divb-pressure-fix), which keeps e - |B|^2 / 2 fixed.  Host arrays are staged one
+ * component at a time and both calls then synchronise the stream. */
+int mg_divb_rhs(mg_tree *t, const double *leaf_B, int order, int on_device);
+int mg_divb_project(mg_tree *t, double *leaf_B, double *leaf_e, int on_device);
+
 /* Kernel timing: when enabled, HIP events bracket every launch of the smoothing
  * kernel on the finest level (on the bound stream); mg_profile_read returns the
  * number of such launches and their total milliseconds since enabling. */

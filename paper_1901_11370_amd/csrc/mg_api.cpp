@@ -119,6 +119,7 @@ size_t plan(mg_tree *t, char *base) {
     size_t o_org = L.take<int32_t>(3 * nb), o_nbr = L.take<int32_t>(6 * nb), o_cf = L.take<int32_t>(6 * nb);
     size_t o_par = L.take<int32_t>(nb), o_dom = L.take<int32_t>(nb), o_lev = L.take<int32_t>(nb);
     size_t o_leaf = L.take<int32_t>(t->nleafblk), o_lf = L.take<int32_t>(T.ndom + 1);
+    size_t o_lrank = L.take<int32_t>(nb);
     size_t o_h = L.take<double>((size_t)T.ndom * MAXLEV * 3), o_nc = L.take<int32_t>((size_t)T.ndom * MAXLEV * 3);
     size_t o_bck = L.take<int32_t>(6 * T.ndom), o_bcv = L.take<double>(6 * T.ndom), o_bc0 = L.take<double>(6 * T.ndom);
     size_t o_toff = L.take<int64_t>((size_t)T.ndom * MAXLEV);
@@ -144,6 +145,9 @@ size_t plan(mg_tree *t, char *base) {
         put(o_lev, T.lev.data(), T.lev.size() * 4);
         put(o_leaf, T.leaf_blk.data(), T.leaf_blk.size() * 4);
         put(o_lf, T.leaf_first.data(), T.leaf_first.size() * 4);
+        std::vector<int32_t> lrank(nb, -1);
+        for (size_t r = 0; r < T.leaf_blk.size(); r++) lrank[T.leaf_blk[r]] = (int32_t)r;
+        put(o_lrank, lrank.data(), lrank.size() * 4);
         put(o_h, T.h.data(), T.h.size() * 8);
         put(o_nc, T.ncell.data(), T.ncell.size() * 4);
         std::vector<int32_t> bck(6 * T.ndom);
@@ -174,6 +178,7 @@ size_t plan(mg_tree *t, char *base) {
         tb.lev = (const int32_t *)P(o_lev);
         tb.leaf_blk = (const int32_t *)P(o_leaf);
         tb.leaf_first = (const int32_t *)P(o_lf);
+        tb.leaf_rank = (const int32_t *)P(o_lrank);
         tb.h = (const double *)P(o_h);
         tb.ncell = (const int32_t *)P(o_nc);
         tb.bck = (const int32_t *)P(o_bck);
@@ -1162,6 +1167,61 @@ int mg_face_gradient(mg_tree *t, const double *leaf_phi, const double *leaf_lamb
         HIP_OR_FAIL(t, hipMemcpyAsync(out, dst, (size_t)t->T.nleaf_cells * 8, hipMemcpyDeviceToHost, t->stream));
         HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));
     }
+    return MG_OK;
+}
+
+// Elliptic divergence cleaning (Sec. 4.1): shared argument checks.
+static int divb_check(mg_tree *t, const double *leaf_B) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!leaf_B) return MG_ERR_ARG;
+    if (t->T.refined) return fail(t, MG_ERR_ARG, "divergence cleaning needs a tree without refinement");
+    if (var(t) || t->prm.helmholtz_lambda != 0.0 || t->prm.axisymmetric)
+        return fail(t, MG_ERR_ARG, "divergence cleaning needs the plain Cartesian Laplacian (eps = 1, lambda = 0)");
+    return MG_OK;
+}
+
+int mg_divb_rhs(mg_tree *t, const double *leaf_B, int order, int on_device) {
+    int rc = divb_check(t, leaf_B);
+    if (rc) return rc;
+    if (order != 2 && order != 4) return fail(t, MG_ERR_ARG, "order must be 2 or 4");
+    const int64_t n = t->T.nleaf_cells;
+    const Launch L = launch(t, false);
+    for (int d = 0; d < t->T.dim; d++) {
+        // a host component goes through the staging buffer (stream order protects it)
+        const double *src = stage_in(t, leaf_B + d * n, on_device, t->d_stage, &rc);
+        if (rc) return rc;
+        launch_divb(L, src, t->d_stage2, d, d > 0, order, n);
+    }
+    K<double>::scatter(L, t->P64.f, t->d_stage2, (int)t->nleafblk);
+    if ((rc = check_launch(t))) return rc;
+    if (!on_device) HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));   // the host buffer may be reused
+    return MG_OK;
+}
+
+int mg_divb_project(mg_tree *t, double *leaf_B, double *leaf_e, int on_device) {
+    int rc = divb_check(t, leaf_B);
+    if (rc) return rc;
+    const int64_t n = t->T.nleaf_cells;
+    const Launch L = launch(t, t->homog);
+    double *e = nullptr;
+    if (leaf_e) {
+        e = on_device ? leaf_e : t->d_stage2;
+        if (!on_device)
+            HIP_OR_FAIL(t, hipMemcpyAsync(e, leaf_e, (size_t)n * 8, hipMemcpyHostToDevice, t->stream));
+    }
+    for (int d = 0; d < t->T.dim; d++) {
+        double *Bd = on_device ? leaf_B + d * n : t->d_stage;
+        if (!on_device)
+            HIP_OR_FAIL(t, hipMemcpyAsync(Bd, leaf_B + d * n, (size_t)n * 8, hipMemcpyHostToDevice, t->stream));
+        launch_divb_project(L, t->P64, Bd, e, d, n);
+        if (!on_device)
+            HIP_OR_FAIL(t, hipMemcpyAsync(leaf_B + d * n, Bd, (size_t)n * 8, hipMemcpyDeviceToHost, t->stream));
+    }
+    if (leaf_e && !on_device)
+        HIP_OR_FAIL(t, hipMemcpyAsync(leaf_e, e, (size_t)n * 8, hipMemcpyDeviceToHost, t->stream));
+    if ((rc = check_launch(t))) return rc;
+    if (!on_device) HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));
     return MG_OK;
 }
 

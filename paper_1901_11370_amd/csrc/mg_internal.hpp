@@ -28,6 +28,7 @@ struct DevTables {
     const int32_t *lev;       // [nb] global level of the block
     const int32_t *leaf_blk;  // [nleaf_blocks] blocks in leaf order
     const int32_t *leaf_first;// [ndom+1] first leaf rank of every domain
+    const int32_t *leaf_rank; // [nb] position of a leaf block in leaf order, -1 for parents
     const double *h;          // [ndom][MAXLEV][3] grid spacing
     const int32_t *ncell;     // [ndom][MAXLEV][3] cells per dimension of the full level grid
     const int32_t *bck;       // [ndom][6] boundary kinds
@@ -146,6 +147,13 @@ void launch_dots(const Launch &L, const double *V, int64_t stride, int k, const 
 void launch_combo(const Launch &L, double *y, const double *V, int64_t stride, const double *coef, int k, double sign,
                   bool overwrite, int64_t n);
 void launch_scale(const Launch &L, double *x, double a, int64_t n);
+// Elliptic divergence cleaning on trees without refinement (leaf-ordered arrays, one
+// component of B at a time): out (+)= dB_d/dx_d, central differences of order 2 or 4.
+void launch_divb(const Launch &L, const double *Bd, double *out, int d, bool accumulate, int order,
+                 int64_t nleaf_cells);
+// B_d -= dphi/dx_d (second-order central differences of P.v with its ghosts); if e is
+// set, e += (B_new^2 - B_old^2) / 2.
+void launch_divb_project(const Launch &L, const Plane<double> &P, double *Bd, double *e, int d, int64_t nleaf_cells);
 void launch_face_gradient(const Launch &L, const Plane<double> &P, const double *lam_blocks,
                           const double *lam_g, double *out_leaf, int nleafblk);
 

@@ -1941,6 +1941,71 @@ __global__ void __launch_bounds__(256) k_face_grad(Plane<double> P, DevTables tb
     }
 }
 
+// ----------------------------------------------- elliptic divergence cleaning
+// Sec. 4.1 on trees without refinement.  B is given per component as a leaf array
+// (leaf block by leaf block, cells x fastest), one thread per leaf cell.
+// The value of component B_d o cells along x_d from local cell (i,j,k) of leaf block
+// b (rank r): a same-level neighbour's cell across the face, or (physical face) the
+// block's boundary cell repeated.  |o| <= 2 <= BS.
+template <int D, int BS>
+__device__ __forceinline__ double divb_at(const double *__restrict__ Bd, const DevTables &tb, int64_t b, int64_t r,
+                                          int t, int cd, int sd, int d, int o) {
+    using g = G<D, BS>;
+    const int q = cd + o;
+    if (q >= 0 && q < BS) return Bd[r * g::NC + t + o * sd];
+    const int side = q >= BS;
+    const int n = tb.nbr[6 * b + 2 * d + side];
+    if (n >= 0) return Bd[(int64_t)tb.leaf_rank[n] * g::NC + t + (side ? o - BS : o + BS) * sd];
+    return Bd[r * g::NC + t + ((side ? BS - 1 : 0) - cd) * sd];
+}
+
+// out (+)= dB_d/dx_d: eq. divb-central-diff (ORDER 2) or eq. divb-4th-order (ORDER 4).
+template <int D, int BS, int ORDER>
+__global__ void __launch_bounds__(256) k_divb(const double *__restrict__ Bd, double *__restrict__ out, DevTables tb,
+                                              int d, int accumulate, int64_t ncells) {
+    using g = G<D, BS>;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= ncells) return;
+    const int64_t r = id / g::NC;
+    const int t = (int)(id % g::NC);
+    const int64_t b = tb.leaf_blk[r];
+    const int i = t % BS, j = (t / BS) % BS, k = D == 3 ? t / (BS * BS) : 0;
+    const int cd = d == 0 ? i : (d == 1 ? j : k);
+    const int sd = d == 0 ? 1 : (d == 1 ? BS : BS * BS);
+    const double h = tb.h[((size_t)tb.dom[b] * MAXLEV + tb.lev[b]) * 3 + d];
+    double der;
+    if (ORDER == 2) {
+        der = (divb_at<D, BS>(Bd, tb, b, r, t, cd, sd, d, 1) - divb_at<D, BS>(Bd, tb, b, r, t, cd, sd, d, -1)) /
+              (2.0 * h);
+    } else {
+        const double p2 = divb_at<D, BS>(Bd, tb, b, r, t, cd, sd, d, 2), p1 = divb_at<D, BS>(Bd, tb, b, r, t, cd, sd, d, 1);
+        const double m1 = divb_at<D, BS>(Bd, tb, b, r, t, cd, sd, d, -1), m2 = divb_at<D, BS>(Bd, tb, b, r, t, cd, sd, d, -2);
+        der = (-p2 + 8.0 * p1 - 8.0 * m1 + m2) / (12.0 * h);
+    }
+    out[id] = accumulate ? out[id] + der : der;
+}
+
+// B_d -= dphi/dx_d (eq. poisson-divb-cleaning, second-order central differences of
+// phi with its ghost cells); e += (B_new^2 - B_old^2) / 2 (eq. divb-pressure-fix).
+template <int D, int BS>
+__global__ void __launch_bounds__(256) k_divb_project(Plane<double> P, double *__restrict__ Bd, double *__restrict__ e,
+                                                      DevTables tb, int d, int64_t ncells) {
+    using g = G<D, BS>;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= ncells) return;
+    const int64_t r = id / g::NC;
+    const int t = (int)(id % g::NC);
+    const int64_t b = tb.leaf_blk[r];
+    const int i = t % BS, j = (t / BS) % BS, k = D == 3 ? t / (BS * BS) : 0;
+    const int di = d == 0, dj = d == 1, dk = d == 2;
+    const double h = tb.h[((size_t)tb.dom[b] * MAXLEV + tb.lev[b]) * 3 + d];
+    const double gp = (ld<D, BS>(P.v, P.vg, b, i + di, j + dj, k + dk) - ld<D, BS>(P.v, P.vg, b, i - di, j - dj, k - dk)) /
+                      (2.0 * h);
+    const double bo = Bd[id], bn = bo - gp;
+    Bd[id] = bn;
+    if (e) e[id] += 0.5 * (bn * bn - bo * bo);
+}
+
 // ================================================================ launchers
 #define HIPCHK(x) (x)
 
@@ -2308,6 +2373,22 @@ void launch_add_norm64(const Launch &L, const Plane<double> &P, const float *e, 
             k_resid<D, BS, false, true, TPB><<<nleafblk, TPB, 0, L.stream>>>(P, L.tb, e, eg, L.partials, rout32,
                                                                              nullptr);
     });
+}
+
+void launch_divb(const Launch &L, const double *Bd, double *out, int d, bool accumulate, int order,
+                 int64_t nleaf_cells) {
+    if (nleaf_cells <= 0) return;
+    const unsigned grid = (unsigned)((nleaf_cells + 255) / 256);
+    DISPATCH_DB(L, {
+        if (order == 4) k_divb<D, BS, 4><<<grid, 256, 0, L.stream>>>(Bd, out, L.tb, d, accumulate ? 1 : 0, nleaf_cells);
+        else k_divb<D, BS, 2><<<grid, 256, 0, L.stream>>>(Bd, out, L.tb, d, accumulate ? 1 : 0, nleaf_cells);
+    });
+}
+
+void launch_divb_project(const Launch &L, const Plane<double> &P, double *Bd, double *e, int d, int64_t nleaf_cells) {
+    if (nleaf_cells <= 0) return;
+    const unsigned grid = (unsigned)((nleaf_cells + 255) / 256);
+    DISPATCH_DB(L, { k_divb_project<D, BS><<<grid, 256, 0, L.stream>>>(P, Bd, e, L.tb, d, nleaf_cells); });
 }
 
 void launch_reduce_norms(const Launch &L) {

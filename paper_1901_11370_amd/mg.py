@@ -82,6 +82,8 @@ _SIGS = {
     "mg_solve": ([_vp, _d, ctypes.c_int, ctypes.c_int, _P(ctypes.c_int)], ctypes.c_int),
     "mg_solve_stats": ([_vp, ctypes.c_int, _P(_d), _P(_d), _P(ctypes.c_int)], ctypes.c_int),
     "mg_face_gradient": ([_vp, _vp, _vp, _vp, ctypes.c_int], ctypes.c_int),
+    "mg_divb_rhs": ([_vp, _vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "mg_divb_project": ([_vp, _vp, _vp, ctypes.c_int], ctypes.c_int),
     "mg_profile_enable": ([_vp, ctypes.c_int], ctypes.c_int),
     "mg_profile_read": ([_vp, _P(_i64), _P(_d), _P(_d)], ctypes.c_int),
     "mg_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -297,6 +299,39 @@ class Tree:
         o = np.zeros(self.n_leaf)
         _check(mg_face_gradient(self.h, p1, p2, o.ctypes.data_as(_vp), 0), self.h)
         return o
+
+    # ------------------------------------------------ divergence cleaning
+    def _field(self, a, ncomp):
+        """(pointer, on_device, array) for a (ncomp, n_leaf) float64 field, in place when
+        it already is a contiguous float64 array or CUDA tensor."""
+        try:
+            import torch
+            if isinstance(a, torch.Tensor) and a.is_cuda:
+                if a.dtype != torch.float64 or not a.is_contiguous():
+                    a = a.detach().to(torch.float64).contiguous()
+                assert a.numel() == ncomp * self.n_leaf
+                return _vp(a.data_ptr()), 1, a
+        except ImportError:
+            pass
+        if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous):
+            a = np.ascontiguousarray(np.asarray(a), dtype=np.float64)
+        assert a.size == ncomp * self.n_leaf
+        return a.ctypes.data_as(_vp), 0, a
+
+    def divb_rhs(self, B, order=2):
+        """f = div B (central differences of order 2 or 4), B of shape (dim, n_leaf)."""
+        p, dev, keep = self._field(B, self.dim)
+        _check(mg_divb_rhs(self.h, p, int(order), dev), self.h)
+
+    def divb_project(self, B, e=None):
+        """B <- B - grad phi and e <- e + (|B_new|^2 - |B_old|^2)/2 with the current phi.
+        Works in place where the arrays allow it; returns (B, e)."""
+        pb, db, b = self._field(B, self.dim)
+        pe, de, ee = (None, db, None) if e is None else self._field(e, 1)
+        if de != db:
+            raise ValueError("B and e must both be on the device or both on the host")
+        _check(mg_divb_project(self.h, pb, pe, db), self.h)
+        return b, ee
 
     # ------------------------------------------------------------- profiling
     def profile_enable(self, on=True):
