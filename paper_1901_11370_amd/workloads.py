@@ -288,3 +288,39 @@ def x1(grid: str = "uniform", base: int = 64) -> Workload:
 
     return Workload(f"convergence_{grid}_{base}", [dom], max_refine=len(boxes), refine=rule if boxes else None,
                     rhs=rhs, note="phi_sol = cos(pi n.x) + 10 exp(-100|x|^2), n = (1,2,3)")
+
+
+# ------------------------------------------------ divergence cleaning (Sec. 4)
+def field_loop_B(dom: Domain, x: np.ndarray, seed: int = 11, amp: float = 2e-4) -> np.ndarray:
+    """Cell-centred magnetic field of shape (dim, n): the field loop of Sec. 4.2
+    (vector potential A_z = A0 (R0 - r) for r <= R0 around the z axis, A0 = 1e-3,
+    R0 = 0.3; B_x = dA_z/dy, B_y = -dA_z/dx by central differences on the cell
+    centres, as the paper sets it up), plus a seeded sum of Gaussian bumps in every
+    component (width^2 0.05, amplitude amp) that gives B a divergence to clean."""
+    dim = dom.dim
+    h = (np.array(dom.hi, dtype=float) - np.array(dom.lo, dtype=float)) / np.array(dom.base_cells, dtype=float)
+    A0, R0 = 1e-3, 0.3
+
+    def Az(p):
+        r = np.sqrt(p[:, 0] ** 2 + p[:, 1] ** 2)
+        return np.where(r <= R0, A0 * (R0 - r), 0.0)
+
+    B = np.zeros((dim, len(x)))
+    ex = np.zeros(dim)
+    ex[0] = h[0]
+    ey = np.zeros(dim)
+    ey[1] = h[1]
+    B[0] = (Az(x + ey) - Az(x - ey)) / (2 * h[1])
+    B[1] = -(Az(x + ex) - Az(x - ex)) / (2 * h[0])
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(np.array(dom.lo) + 0.2, np.array(dom.hi) - 0.2, size=(4, dim))
+    for a in range(dim):
+        for ck in c:
+            B[a] += amp * rng.normal() * np.exp(-np.sum((x - ck) ** 2, axis=1) / 0.05)
+    return B
+
+
+def divb_periodic(n: int, dim: int = 3) -> Workload:
+    """Periodic box [-1,1]^dim of n^dim cells in 16^dim blocks for the cleaning runs."""
+    dom = Domain(dim, [n] * dim, [-1.0] * dim, [1.0] * dim, [PERIODIC] * (2 * dim))
+    return Workload(f"divb_periodic{dim}d_{n}", [dom], bs=16)

@@ -24,28 +24,7 @@ def _centres(t, w):
 
 
 def _field(w, x, seed):
-    """Field-loop B (A_z = A0 (R0 - r) inside r <= R0, B = curl A by central
-    differences on the cell centres) plus a seeded perturbation with a divergence."""
-    d = w.domains[0]
-    dim = d.dim
-    h = (np.array(d.hi) - np.array(d.lo)) / np.array(d.base_cells)
-    A0, R0 = 1e-3, 0.3
-
-    def Az(p):
-        r = np.sqrt(p[:, 0] ** 2 + p[:, 1] ** 2)
-        return np.where(r <= R0, A0 * (R0 - r), 0.0)
-
-    B = np.zeros((dim, len(x)))
-    ex = np.zeros(dim); ex[0] = h[0]
-    ey = np.zeros(dim); ey[1] = h[1]
-    B[0] = (Az(x + ey) - Az(x - ey)) / (2 * h[1])
-    B[1] = -(Az(x + ex) - Az(x - ex)) / (2 * h[0])
-    rng = np.random.default_rng(seed)
-    c = rng.uniform(np.array(d.lo) + 0.2, np.array(d.hi) - 0.2, size=(4, dim))
-    for a in range(dim):
-        for ck in c:
-            B[a] += 2e-4 * rng.normal() * np.exp(-np.sum((x - ck) ** 2, axis=1) / 0.05)
-    return B
+    return W.field_loop_B(w.domains[0], x, seed)
 
 
 def _case(name):
