@@ -33,6 +33,7 @@ struct mg_tree {
     bool homog = false;
     // device views
     DevTables tb{}, tb0{};          // real boundary values / homogeneous
+    uint64_t tail_lds[2] = {0, 0};  // domains whose coarse grids fit in LDS (FP64, FP32)
     Plane<double> P64{};
     Plane<float> P32{};
     std::vector<int32_t *> d_parents, d_cfs;
@@ -261,7 +262,27 @@ Launch launch(mg_tree *t, bool homogeneous) {
     L.coarse_steps = t->d_steps;
     L.partials = t->d_partials;
     L.dom_norms = t->d_domnorms;
+    L.tail_lds[0] = t->tail_lds[0];
+    L.tail_lds[1] = t->tail_lds[1];
     return L;
+}
+
+// Domains whose coarse grids (v and f of every grid, v_old below the top grid, eps)
+// fit in the coarse solver's LDS for fields of `bytes` bytes; the solver kernel makes
+// the same test.
+uint64_t tail_fit_mask(const HostTree &T, int bytes, bool var) {
+    uint64_t m = 0;
+    for (int dm = 0; dm < T.ndom && dm < 64; dm++) {
+        const int top = T.tail_top[dm];
+        const int64_t first = T.tail_off[(size_t)dm * MAXLEV];
+        const int32_t *nc = &T.ncell[((size_t)dm * MAXLEV + top) * 3];
+        const int64_t last = (int64_t)(nc[0] + 2) * (nc[1] + 2) * (T.dim == 3 ? nc[2] + 2 : 1);
+        const int64_t n = T.tail_off[(size_t)dm * MAXLEV + top] + last - first;
+        const int64_t nold = T.tail_off[(size_t)dm * MAXLEV + top] - first;
+        const int64_t need = (2 * n + nold + (var ? n : 0)) * bytes;
+        if (need <= tail_lds_bytes()) m |= 1ull << dm;
+    }
+    return m;
 }
 
 uint64_t all_mask(const mg_tree *t) {
@@ -821,6 +842,8 @@ int mg_tree_create(const mg_domain *domains, int n_domains, int block_size, int 
         return MG_ERR_ARG;
     }
     t->need = plan(t, nullptr);
+    t->tail_lds[0] = tail_fit_mask(t->T, 8, p.variable_eps != 0);
+    t->tail_lds[1] = tail_fit_mask(t->T, 4, p.variable_eps != 0);
     *out = t;
     return MG_OK;
 }

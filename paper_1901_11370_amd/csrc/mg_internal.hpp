@@ -82,6 +82,8 @@ struct Launch {
     int32_t *coarse_steps;      // [ndom] device: steps taken by the last coarsest solve
     double *partials;           // [nleaf_blocks][4] device scratch
     double *dom_norms;          // [ndom][4] device: max|r|, sum vol r^2, max|f|, sum vol f^2
+    uint64_t tail_lds[2];       // domains whose coarse grids fit in the coarse solver's LDS:
+                                // [0] FP64 fields, [1] FP32 fields
 };
 
 // Kernel launchers (mg_kernels.hip).  `b0, nb` is a contiguous block range of one
@@ -126,6 +128,8 @@ enum { TAIL_VCYCLE = 0, TAIL_FMG = 1 };
 // Kernel attributes set once per process before any launch (large dynamic LDS of the
 // coarse-grid kernel).
 void prepare_kernels();
+// LDS bytes the single-workgroup coarse solver has for a domain's grids.
+int tail_lds_bytes();
 
 // FP64 composite residual over the leaf blocks; optionally writes r (cast) into rout.
 void launch_norm64(const Launch &L, const Plane<double> &P, int nleafblk, bool var, float *rout32,

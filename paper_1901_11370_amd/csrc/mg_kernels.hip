@@ -572,7 +572,7 @@ __global__ void __launch_bounds__(256) k_ghost(Plane<T> P, DevTables tb, int b0,
     using g = G<D, BS>;
     const int64_t b = list ? list[blockIdx.x] : b0 + blockIdx.x;
     if (!((mask >> tb.dom[b]) & 1)) return;
-    for (int t = threadIdx.x; t < g::NG; t += blockDim.x) {
+    for (int t = threadIdx.x; t < g::NG; t += (g::NG < 256 ? g::NG : 256)) {
         int f = t / g::NF, r = t % g::NF;
         ghost_cell<T, D, BS, EPS>(P, tb, b, f, r % BS, r / BS, cf_only != 0);
     }
@@ -736,7 +736,7 @@ __global__ void __launch_bounds__(256) k_fas(Plane<T> P, DevTables tb, int lev, 
                                              uint64_t mask, int wg_per_block) {
     using g = G<D, BS>;
     const int64_t b = list[blockIdx.x / wg_per_block];
-    const int t = (blockIdx.x % wg_per_block) * blockDim.x + threadIdx.x;
+    const int t = (blockIdx.x % wg_per_block) * 256 + threadIdx.x;
     // the domain test comes last so that the data loads need not wait for it
     const int dm = tb.dom[b];
     if (t < g::NC) {
@@ -903,8 +903,15 @@ __device__ __forceinline__ int tix(const TailLev &g, int i, int j, int k) {
     return g.off + (D == 3 ? (k + 1) * g.sz : 0) + (j + 1) * g.sy + (i + 1);
 }
 
+// Threads of the single-workgroup coarse solver (the variable-coefficient code needs
+// more registers).  Kernels use this constant rather than the block size at run time,
+// which the device library reads from memory at every use.
+template <bool VAR>
+constexpr int tail_threads() { return VAR ? 512 : 1024; }
+
 template <typename T, int D, bool VAR>
 struct Tail {
+    static constexpr int NT = tail_threads<VAR>();
     const TailLev *lv;         // [levels] in LDS
     TailBC bc;                 // boundary data (registers)
     double *red;               // reduction scratch in LDS, one slot per wave
@@ -966,7 +973,7 @@ struct Tail {
             const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
             const int n1 = g.n[t1], n2 = D == 3 ? g.n[t2] : 1;
             const int tot = 2 * n1 * n2;
-            for (int q = threadIdx.x; q < tot; q += blockDim.x) {
+            for (int q = threadIdx.x; q < tot; q += NT) {
                 const int side = q >= n1 * n2;
                 const int r = q - side * n1 * n2;
                 int c[3], in[3], op[3];
@@ -1021,7 +1028,7 @@ struct Tail {
         const TailLev g = lv[lev];
         const bool gp = g.ghost_pass;
         const int ns = nslot(g);
-        for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+        for (int s = threadIdx.x; s < ns; s += NT) {
             int i, j, k;
             if (!slot(g, s, colour, i, j, k)) continue;
             T w[6], nb[6];
@@ -1062,12 +1069,12 @@ struct Tail {
     __device__ __forceinline__ void jacobi_step(int lev) const {
         constexpr int R = 8;
         const TailLev g = lv[lev];
-        const bool regs = g.ncell <= R * (int)blockDim.x;
+        const bool regs = g.ncell <= R * NT;
         T nv[R];
         if (regs) {
 #pragma unroll
             for (int r = 0; r < R; r++) {
-                const int c = threadIdx.x + r * blockDim.x;
+                const int c = threadIdx.x + r * NT;
                 if (c < g.ncell) {
                     int i, j, k;
                     cell(g, c, i, j, k);
@@ -1075,7 +1082,7 @@ struct Tail {
                 }
             }
         } else {
-            for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
+            for (int c = threadIdx.x; c < g.ncell; c += NT) {
                 int i, j, k;
                 cell(g, c, i, j, k);
                 ttmp[tix<D>(g, i, j, k)] = jacobi_value(g, i, j, k);
@@ -1085,7 +1092,7 @@ struct Tail {
         if (regs) {
 #pragma unroll
             for (int r = 0; r < R; r++) {
-                const int c = threadIdx.x + r * blockDim.x;
+                const int c = threadIdx.x + r * NT;
                 if (c < g.ncell) {
                     int i, j, k;
                     cell(g, c, i, j, k);
@@ -1094,7 +1101,7 @@ struct Tail {
                 }
             }
         } else {
-            for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
+            for (int c = threadIdx.x; c < g.ncell; c += NT) {
                 int i, j, k;
                 cell(g, c, i, j, k);
                 const T x = ttmp[tix<D>(g, i, j, k)];
@@ -1123,7 +1130,7 @@ struct Tail {
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
         __syncthreads();
         x = red[0];
-        for (int w = 1; w < (int)(blockDim.x >> 6); w++)
+        for (int w = 1; w < (int)(NT >> 6); w++)
             if (red[w] > x || red[w] != red[w]) x = red[w];
         __syncthreads();
         return x;
@@ -1133,7 +1140,7 @@ struct Tail {
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
         __syncthreads();
         x = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); w++) x += red[w];
+        for (int w = 0; w < (int)(NT >> 6); w++) x += red[w];
         __syncthreads();
         return x;
     }
@@ -1141,7 +1148,7 @@ struct Tail {
     __device__ __forceinline__ double resmax(int lev) const {
         const TailLev g = lv[lev];
         double m = 0.0;
-        for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
+        for (int c = threadIdx.x; c < g.ncell; c += NT) {
             int i, j, k;
             cell(g, c, i, j, k);
             const double r = fabs((double)(tf[tix<D>(g, i, j, k)] - Lv(g, i, j, k)));
@@ -1154,11 +1161,11 @@ struct Tail {
     __device__ __forceinline__ void fas(int lev) const {
         const TailLev g = lv[lev];
         if (tvold_top && lev == top) {
-            for (int q = threadIdx.x; q < g.npad; q += blockDim.x) tvold_top[g.off + q] = tv[g.off + q];
+            for (int q = threadIdx.x; q < g.npad; q += NT) tvold_top[g.off + q] = tv[g.off + q];
         } else {
-            for (int q = threadIdx.x; q < g.npad; q += blockDim.x) tvold[g.off + q] = tv[g.off + q];
+            for (int q = threadIdx.x; q < g.npad; q += NT) tvold[g.off + q] = tv[g.off + q];
         }
-        for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
+        for (int c = threadIdx.x; c < g.ncell; c += NT) {
             int i, j, k;
             cell(g, c, i, j, k);
             tf[tix<D>(g, i, j, k)] += Lv(g, i, j, k);
@@ -1175,7 +1182,7 @@ struct Tail {
     // then the FAS right-hand side there.
     __device__ __forceinline__ void restrict_fas(int lev) const {
         const TailLev gf = lv[lev], gc = lv[lev - 1];
-        for (int c = threadIdx.x; c < gc.ncell; c += blockDim.x) {
+        for (int c = threadIdx.x; c < gc.ncell; c += NT) {
             int I, J, K;
             cell(gc, c, I, J, K);
             T sv = T(0), sr = T(0);
@@ -1199,7 +1206,7 @@ struct Tail {
     // with the ghosts of lev pushed.
     __device__ __forceinline__ void correct(int lev) const {
         const TailLev gf = lv[lev], gc = lv[lev - 1];
-        for (int c = threadIdx.x; c < gf.ncell; c += blockDim.x) {
+        for (int c = threadIdx.x; c < gf.ncell; c += NT) {
             int i, j, k;
             cell(gf, c, i, j, k);
             const int p[3] = {i >> 1, j >> 1, k >> 1};
@@ -1230,13 +1237,13 @@ struct Tail {
         for (int f = 0; f < 2 * D; f++) per = per && bc.kind[f] == MG_BC_PERIODIC;
         if (per) {
             double s = 0.0;
-            for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
+            for (int c = threadIdx.x; c < g.ncell; c += NT) {
                 int i, j, k;
                 cell(g, c, i, j, k);
                 s += (double)tf[tix<D>(g, i, j, k)];
             }
             const double mean = reduce_sum(s) / (double)g.ncell;
-            for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
+            for (int c = threadIdx.x; c < g.ncell; c += NT) {
                 int i, j, k;
                 cell(g, c, i, j, k);
                 tf[tix<D>(g, i, j, k)] -= T(mean);
@@ -1367,9 +1374,14 @@ __device__ __forceinline__ void tail_setup(const DevTables &tb, int dm, int nlev
 
 // One workgroup per domain in the mask: the grids 0..tail_top of the domain run a
 // V-cycle or an FMG cycle.
-template <typename T, int D, bool VAR>
-__global__ void __launch_bounds__(VAR ? 512 : 1024) k_tail(Plane<T> P, DevTables tb, int mode, uint64_t mask,
-                                                           TailParams tp, int32_t *steps_out, int lds_bytes) {
+// LDS: the domain's grids are copied into LDS and cycled there (the host launches
+// this form only for domains whose grids fit); else they are cycled in global memory.
+// The two forms are separate kernels: each holds one copy of the cycle code, which
+// keeps the instruction footprint within the instruction cache.
+template <typename T, int D, bool VAR, bool LDS>
+__global__ void __launch_bounds__(tail_threads<VAR>()) k_tail(Plane<T> P, DevTables tb, int mode, uint64_t mask,
+                                                              TailParams tp, int32_t *steps_out, int lds_bytes) {
+    constexpr int NT = tail_threads<VAR>();
     extern __shared__ double smem[];
     __shared__ double red[16];
     __shared__ TailLev lvs[MAXLEV];
@@ -1390,23 +1402,27 @@ __global__ void __launch_bounds__(VAR ? 512 : 1024) k_tail(Plane<T> P, DevTables
     const int nold = (int)(tail_last_off(tb, dm, top) - first);    // v_old cells below the top grid
     const int64_t lds_need = (2 * (int64_t)n + nold + (VAR ? n : 0)) * (int64_t)sizeof(T);
     int steps;
-    if (lds_need <= lds_bytes) {
+    if (LDS) {
+        if (lds_need > lds_bytes) {   // the host's fit test disagrees: leave the grids untouched
+            if (threadIdx.x == 0) steps_out[dm] = -1;
+            return;
+        }
         T *sv = reinterpret_cast<T *>(smem);
         T *sf = sv + n, *so = sf + n, *se = so + nold;
         __syncthreads();
         const TailLev &g = lvs[top];
-        for (int q = threadIdx.x; q < g.npad; q += blockDim.x) {
+        for (int q = threadIdx.x; q < g.npad; q += NT) {
             const T a = P.tv[first + g.off + q], c = P.tf[first + g.off + q];
             sv[g.off + q] = a;
             sf[g.off + q] = c;
         }
         if (VAR)
-            for (int q = threadIdx.x; q < n; q += blockDim.x) se[q] = P.teps[first + q];
+            for (int q = threadIdx.x; q < n; q += NT) se[q] = P.teps[first + q];
         __syncthreads();
         const Tail<T, D, VAR> tl{lvs, bcs, red, sv, so, sf, VAR ? se : nullptr, P.tvold + first, top,
                                  P.tv2 ? P.tv2 + first : nullptr, tp.jacobi, tp.omega};
         steps = tl.run(ops, nops, tp);
-        for (int q = threadIdx.x; q < g.npad; q += blockDim.x) P.tv[first + g.off + q] = sv[g.off + q];
+        for (int q = threadIdx.x; q < g.npad; q += NT) P.tv[first + g.off + q] = sv[g.off + q];
     } else {
         __syncthreads();
         const Tail<T, D, VAR> tl{lvs, bcs, red, P.tv + first, P.tvold + first, P.tf + first,
@@ -1419,7 +1435,8 @@ __global__ void __launch_bounds__(VAR ? 512 : 1024) k_tail(Plane<T> P, DevTables
 
 // eps on the tail grids: restrict down from the top tail grid, then ghost layers.
 template <typename T, int D>
-__global__ void __launch_bounds__(512) k_tail_eps(Plane<T> P, DevTables tb, int nt) {
+__global__ void __launch_bounds__(tail_threads<true>()) k_tail_eps(Plane<T> P, DevTables tb, int nt) {
+    constexpr int NT = tail_threads<true>();
     __shared__ double red[16];
     __shared__ TailLev lvs[MAXLEV];
     __shared__ TailBC bcs;
@@ -1432,7 +1449,7 @@ __global__ void __launch_bounds__(512) k_tail_eps(Plane<T> P, DevTables tb, int 
                               nullptr, nt - 1, nullptr, 0, 0.0};
     for (int l = nt - 1; l >= 1; l--) {
         const TailLev &gf = lvs[l], &gc = lvs[l - 1];
-        for (int c = threadIdx.x; c < gc.ncell; c += blockDim.x) {
+        for (int c = threadIdx.x; c < gc.ncell; c += NT) {
             int I, J, K;
             tl.cell(gc, c, I, J, K);
             T s = T(0);
@@ -1513,7 +1530,7 @@ template <typename T, int D, bool VAR>
 __global__ void __launch_bounds__(256) k_ugsrb(Plane<T> P, DevTables tb, UGrid g, int colour) {
     const int half = g.n[0] / 2;
     const int64_t nh = (int64_t)half * g.n[1] * (D == 3 ? g.n[2] : 1);
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= nh) return;
     const int row = (int)(q / half), pos = (int)(q % half);
     const int j = row % g.n[1], k = D == 3 ? row / g.n[1] : 0;
@@ -1536,7 +1553,7 @@ template <typename T, int D, bool VAR>
 __global__ void __launch_bounds__(256) k_ujacobi(Plane<T> P, const T *src, T *dst, DevTables tb, UGrid g,
                                                  double omega) {
     const int64_t n = (int64_t)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1);
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= n) return;
     const int i = (int)(q % g.n[0]);
     const int r = (int)(q / g.n[0]);
@@ -1561,7 +1578,7 @@ __global__ void __launch_bounds__(256) k_ujacobi(Plane<T> P, const T *src, T *ds
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_ughost(Plane<T> P, DevTables tb, UGrid g) {
     const int64_t n = (int64_t)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1);
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= n) return;
     const int i = (int)(q % g.n[0]);
     const int r = (int)(q / g.n[0]);
@@ -1574,7 +1591,7 @@ __global__ void __launch_bounds__(256) k_ughost(Plane<T> P, DevTables tb, UGrid 
 template <typename T, int D, bool VAR>
 __global__ void __launch_bounds__(256) k_ufas(Plane<T> P, DevTables tb, UGrid g) {
     const int64_t npad = (int64_t)(g.n[0] + 2) * (g.n[1] + 2) * (D == 3 ? g.n[2] + 2 : 1);
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= npad) return;
     P.tvold[g.off + q] = P.tv[g.off + q];
     const int i = (int)(q % (g.n[0] + 2)) - 1;
@@ -1592,7 +1609,7 @@ __global__ void __launch_bounds__(256) k_ufas(Plane<T> P, DevTables tb, UGrid g)
 template <typename T, int D, bool VAR>
 __global__ void __launch_bounds__(256) k_urestrict(Plane<T> P, DevTables tb, UGrid g, UGrid gc) {
     const int64_t n = (int64_t)gc.n[0] * gc.n[1] * (D == 3 ? gc.n[2] : 1);
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= n) return;
     const int I = (int)(q % gc.n[0]);
     const int r = (int)(q / gc.n[0]);
@@ -1618,7 +1635,7 @@ __global__ void __launch_bounds__(256) k_urestrict(Plane<T> P, DevTables tb, UGr
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_ucorrect(Plane<T> P, DevTables tb, UGrid g, UGrid gc) {
     const int64_t n = (int64_t)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1);
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= n) return;
     const int i = (int)(q % g.n[0]);
     const int r = (int)(q / g.n[0]);
@@ -1644,15 +1661,15 @@ __global__ void __launch_bounds__(256) k_ucorrect(Plane<T> P, DevTables tb, UGri
 // ------------------------------------------------------------ small utilities
 template <typename T>
 __global__ void k_fill(T *p, size_t n, T value) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * 256;
     for (; i < n; i += stride) p[i] = value;
 }
 
 template <typename T>
 __global__ void k_copy(T *dst, const T *src, size_t n) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * 256;
     for (; i < n; i += stride) dst[i] = src[i];
 }
 
@@ -1662,7 +1679,7 @@ __global__ void __launch_bounds__(256) k_scatter(T *blk, double *user, DevTables
     using g = G<D, BS>;
     const int64_t rank = blockIdx.x / wg_per_block;
     const int64_t b = tb.leaf_blk[rank];
-    const int t = (blockIdx.x % wg_per_block) * blockDim.x + threadIdx.x;
+    const int t = (blockIdx.x % wg_per_block) * (g::NC < 256 ? g::NC : 256) + threadIdx.x;
     if (t >= g::NC) return;
     int i = t % BS, j = (t / BS) % BS, k = D == 3 ? t / (BS * BS) : 0;
     int64_t o = b * g::NC + g::in(i, j, k);
@@ -1863,7 +1880,7 @@ __global__ void __launch_bounds__(256) k_reduce_norms(DevTables tb, const double
     const int dm = blockIdx.x;
     const int r0 = tb.leaf_first[dm], r1 = tb.leaf_first[dm + 1];
     double mr = 0, sr = 0, mf = 0, sf = 0;
-    for (int r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    for (int r = r0 + threadIdx.x; r < r1; r += 256) {
         const double *p = partials + 4 * (int64_t)r;
         if (p[0] > mr || p[0] != p[0]) mr = p[0];
         sr += p[1];
@@ -1872,7 +1889,7 @@ __global__ void __launch_bounds__(256) k_reduce_norms(DevTables tb, const double
     }
     sm[0][threadIdx.x] = mr; sm[1][threadIdx.x] = sr; sm[2][threadIdx.x] = mf; sm[3][threadIdx.x] = sf;
     __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    for (int st = 256 / 2; st > 0; st >>= 1) {
         if (threadIdx.x < st) {
             double o = sm[0][threadIdx.x + st];
             if (o > sm[0][threadIdx.x] || o != o) sm[0][threadIdx.x] = o;
@@ -1894,7 +1911,7 @@ __global__ void __launch_bounds__(256) k_add_leaf(double *v64, double *vg64, con
     using g = G<D, BS>;
     const int64_t rank = blockIdx.x / wg_per_block;
     const int64_t b = tb.leaf_blk[rank];
-    const int t = (blockIdx.x % wg_per_block) * blockDim.x + threadIdx.x;
+    const int t = (blockIdx.x % wg_per_block) * (g::NC < 256 ? g::NC : 256) + threadIdx.x;
     if (t >= g::NC) return;
     BlockCtx<D> cx;
     cx.load(tb, b, tb.lev[b]);
@@ -1915,7 +1932,7 @@ __global__ void __launch_bounds__(256) k_face_grad(Plane<double> P, DevTables tb
     const int dm = tb.dom[b], lev = tb.lev[b];
     const Spacing s = spacing(tb, dm, lev);
     {
-        const int t = (blockIdx.x % wg_per_block) * blockDim.x + threadIdx.x;
+        const int t = (blockIdx.x % wg_per_block) * (g::NC < 256 ? g::NC : 256) + threadIdx.x;
         if (t >= g::NC) return;
         int i = t % BS, j = (t / BS) % BS, k = D == 3 ? t / (BS * BS) : 0;
         int c = g::in(i, j, k);
@@ -1964,7 +1981,7 @@ template <int D, int BS, int ORDER>
 __global__ void __launch_bounds__(256) k_divb(const double *__restrict__ Bd, double *__restrict__ out, DevTables tb,
                                               int d, int accumulate, int64_t ncells) {
     using g = G<D, BS>;
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (id >= ncells) return;
     const int64_t r = id / g::NC;
     const int t = (int)(id % g::NC);
@@ -1991,7 +2008,7 @@ template <int D, int BS>
 __global__ void __launch_bounds__(256) k_divb_project(Plane<double> P, double *__restrict__ Bd, double *__restrict__ e,
                                                       DevTables tb, int d, int64_t ncells) {
     using g = G<D, BS>;
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (id >= ncells) return;
     const int64_t r = id / g::NC;
     const int t = (int)(id % g::NC);
@@ -2020,7 +2037,7 @@ template <typename S, int D, int BS, bool TO_BLOCKS>
 __global__ void __launch_bounds__(256) k_vec_blocks(S *blk, double *vec, DevTables tb, int wg_per_block) {
     using g = G<D, BS>;
     const int64_t rank = blockIdx.x / wg_per_block;
-    const int t = (blockIdx.x % wg_per_block) * blockDim.x + threadIdx.x;
+    const int t = (blockIdx.x % wg_per_block) * (g::NC < 256 ? g::NC : 256) + threadIdx.x;
     if (t >= g::NC) return;
     const int64_t b = tb.leaf_blk[rank];
     if (TO_BLOCKS) blk[b * g::NC + t] = (S)vec[rank * g::NC + t];
@@ -2192,33 +2209,44 @@ static void allow_lds(K kernel) {
 }
 
 void prepare_kernels() {
-    allow_lds(k_tail<double, 3, true>);
-    allow_lds(k_tail<double, 3, false>);
-    allow_lds(k_tail<double, 2, true>);
-    allow_lds(k_tail<double, 2, false>);
-    allow_lds(k_tail<float, 3, true>);
-    allow_lds(k_tail<float, 3, false>);
-    allow_lds(k_tail<float, 2, true>);
-    allow_lds(k_tail<float, 2, false>);
+    allow_lds(k_tail<double, 3, true, true>);
+    allow_lds(k_tail<double, 3, false, true>);
+    allow_lds(k_tail<double, 2, true, true>);
+    allow_lds(k_tail<double, 2, false, true>);
+    allow_lds(k_tail<float, 3, true, true>);
+    allow_lds(k_tail<float, 3, false, true>);
+    allow_lds(k_tail<float, 2, true, true>);
+    allow_lds(k_tail<float, 2, false, true>);
+}
+
+template <typename T, int D, bool VAR>
+static void launch_tail(const Launch &L, const Plane<T> &P, int mode, uint64_t mask, const TailParams &tp) {
+    constexpr int TPB = tail_threads<VAR>();
+    const uint64_t fit = L.tail_lds[sizeof(T) == 4 ? 1 : 0];
+    if (mask & fit)
+        k_tail<T, D, VAR, true><<<L.ndom, TPB, kTailLds, L.stream>>>(P, L.tb, mode, mask & fit, tp, L.coarse_steps,
+                                                                     kTailLds);
+    if (mask & ~fit)
+        k_tail<T, D, VAR, false><<<L.ndom, TPB, 0, L.stream>>>(P, L.tb, mode, mask & ~fit, tp, L.coarse_steps, 0);
 }
 
 template <typename T>
 void K<T>::tail(const Launch &L, const Plane<T> &P, int mode, uint64_t mask, const TailParams &tp, bool var) {
-    const int TPB = var ? 512 : 1024;   // the variable-coefficient code needs more registers
-    const int lds = kTailLds;
     if (L.dim == 3) {
-        if (var) k_tail<T, 3, true><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, mode, mask, tp, L.coarse_steps, lds);
-        else k_tail<T, 3, false><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, mode, mask, tp, L.coarse_steps, lds);
+        if (var) launch_tail<T, 3, true>(L, P, mode, mask, tp);
+        else launch_tail<T, 3, false>(L, P, mode, mask, tp);
     } else {
-        if (var) k_tail<T, 2, true><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, mode, mask, tp, L.coarse_steps, lds);
-        else k_tail<T, 2, false><<<L.ndom, TPB, lds, L.stream>>>(P, L.tb, mode, mask, tp, L.coarse_steps, lds);
+        if (var) launch_tail<T, 2, true>(L, P, mode, mask, tp);
+        else launch_tail<T, 2, false>(L, P, mode, mask, tp);
     }
 }
 
+int tail_lds_bytes() { return kTailLds; }
+
 template <typename T>
 void K<T>::tail_eps(const Launch &L, const Plane<T> &P) {
-    if (L.dim == 3) k_tail_eps<T, 3><<<L.ndom, 512, 0, L.stream>>>(P, L.tb, L.nt);
-    else k_tail_eps<T, 2><<<L.ndom, 512, 0, L.stream>>>(P, L.tb, L.nt);
+    if (L.dim == 3) k_tail_eps<T, 3><<<L.ndom, tail_threads<true>(), 0, L.stream>>>(P, L.tb, L.nt);
+    else k_tail_eps<T, 2><<<L.ndom, tail_threads<true>(), 0, L.stream>>>(P, L.tb, L.nt);
 }
 
 static inline unsigned ublocks(int64_t n) { return (unsigned)((n + 255) / 256); }
