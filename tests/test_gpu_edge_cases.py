@@ -1,0 +1,83 @@
+"""Degenerate and boundary cases of the GPU path against the reference solver (the
+FP64 bar of 1e-11 relative after the same cycles): one-block domains (the whole
+hierarchy below the block runs in the single-workgroup coarse solver), the smallest
+block size on a one-block grid, coarsest grids of 3, 5 and 7 cells per axis with
+periodic wrap (odd periodic coarse grids), refinement that wraps across a periodic
+boundary, a forest that mixes a one-block domain with larger ones, and f = 0 (Laplace
+with boundary values, where the residual norm is absolute).
+"""
+import numpy as np
+import pytest
+
+from helpers import gpu_tree, inputs, oracle_trees, rel_err, split
+from paper_1901_11370_amd import workloads as W
+from test_gpu_parity import _run
+
+pytestmark = pytest.mark.gpu
+
+
+def _gauss_workload(name, dom, bs, remove_mean=False, **kw):
+    rng = np.random.default_rng(17)
+    lo, hi = np.array(dom.lo, float), np.array(dom.hi, float)
+    c = lo + rng.uniform(0.2, 0.8, size=(3, dom.dim)) * (hi - lo)
+    g = W.Gaussians(c, np.array([1.0, -0.7, 0.4]), np.array([0.15, 0.1, 0.2]) * (hi - lo).min())
+
+    def rhs(i, lay):
+        f = g(W.cell_centres(lay, dom))
+        return f - f.mean() if remove_mean else f
+    return W.Workload(name, [dom], bs=bs, rhs=rhs, **kw)
+
+
+@pytest.mark.parametrize("case", ["single_block_2d", "single_block_3d_periodic", "one_block_bs4"])
+def test_one_block_domains(case):
+    if case == "single_block_2d":
+        dom = W.Domain(2, [16, 16], [0, 0], [1, 1], [W.DIRICHLET] * 4, [1.0, -1.0, 0.5, 0.0])
+        _run(_gauss_workload(case, dom, 16), "fvvnv")
+    elif case == "single_block_3d_periodic":
+        dom = W.Domain(3, [16, 16, 16], [0, 0, 0], [1, 1, 1], [W.PERIODIC] * 6)
+        _run(_gauss_workload(case, dom, 16, remove_mean=True), "fvv", remove_mean=True)
+    else:
+        dom = W.Domain(2, [4, 4], [0, 0], [1, 1], [W.NEUMANN, W.DIRICHLET, W.DIRICHLET, W.NEUMANN],
+                       [0.5, 1.0, -0.5, 0.0])
+        _run(_gauss_workload(case, dom, 4), "vvfv")
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_odd_periodic_coarsest_grids(dim):
+    # 7*16 x 5*16 (x 3*16): the coarsest grid has 7 x 5 (x 3) cells, odd along every
+    # periodic axis, so a colour's ghosts are refilled after each half-sweep there
+    n = [112, 80] if dim == 2 else [48, 80, 112]
+    dom = W.Domain(dim, n, [0.0] * dim, [float(x) / 80 for x in n], [W.PERIODIC] * (2 * dim))
+    _run(_gauss_workload(f"odd{dim}", dom, 16, remove_mean=True), "fvv", remove_mean=True)
+
+
+def test_refinement_wrapping_a_periodic_boundary():
+    # refined blocks around the corner (0,0) of a periodic square: the refined region
+    # continues across every periodic face, so coarse-fine faces meet the wrap
+    dom = W.Domain(2, [64, 64], [0, 0], [1, 1], [W.PERIODIC] * 4)
+
+    def refine(d, level, origin, bs):
+        h = 1.0 / (64 << level)
+        c = (np.array(origin[:2], float) + bs / 2) * h
+        c = np.minimum(c, 1 - c)        # distance to the corner through the wrap
+        return level < 2 and float(np.hypot(*c)) < 0.25 / (level + 1)
+
+    w = _gauss_workload("wrap", dom, 8, remove_mean=True, max_refine=2, refine=refine)
+    _run(w, "fvvn", remove_mean=True)
+
+
+def test_forest_with_a_one_block_domain():
+    w = W.config5(sizes=(16, 48, 64))
+    _run(w, "fvvn")
+
+
+def test_laplace_with_boundary_values():
+    # f = 0: the solution is set by the boundary values alone; the relative residual
+    # norm has no right-hand side to scale by and is reported as the absolute one
+    dom = W.Domain(3, [32, 32, 32], [0, 0, 0], [1, 1, 1], [W.DIRICHLET] * 6, [1.0, 0.0, 0.5, -0.5, 0.25, 0.0])
+    w = W.Workload("laplace", [dom], bs=16, rhs=lambda i, lay: np.zeros(len(lay)))
+    t, refs = _run(w, "fvv")
+    r0, _ = t.residual_norm()
+    t.vcycle(3)
+    r1, _ = t.residual_norm()
+    assert np.isfinite(r0) and r1 < 5e-3 * r0   # three cycles at about 0.1 each
