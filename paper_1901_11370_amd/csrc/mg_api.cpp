@@ -315,6 +315,9 @@ struct Driver {
     Launch L;
     Plane<T> P;
     bool v;   // variable eps
+    // The first half-sweep of the next smoothing starts from v = 0 on its level: it
+    // reads neither colour's old values (set for correction solves from e = 0).
+    bool zero_first = false;
 
     void ghost_level(int l, uint64_t m) { K<T>::ghost(L, P, lvb0(t, l), lvnb(t, l), nullptr, 0, m, false, false); }
 
@@ -368,7 +371,9 @@ struct Driver {
                         t->ev_used += 2;
                     }
                 }
-                K<T>::gsrb(L, P, l, lvb0(t, l), lvnb(t, l), c, m, v, e0, e1);
+                const bool z = zero_first && s == 0 && c == 0;
+                K<T>::gsrb(L, P, l, lvb0(t, l), lvnb(t, l), c, m, v, e0, e1, z);
+                zero_first = false;
                 if (ncf) cf_refresh(l, m);
             }
     }
@@ -604,9 +609,20 @@ int worst(const mg_tree *t, const std::vector<double> &n, double *mx, double *l2
 void ir_enqueue(mg_tree *t, bool use_fmg, bool defer_add = false) {
     Driver<float> D = d32(t);
     const Plane<float> &P = t->P32;
-    K<float>::zero(D.L, P.v, (size_t)(t->nb * t->nc));
-    K<float>::zero(D.L, P.vg, (size_t)(t->nb * t->ng));
-    K<float>::zero(D.L, P.tv, (size_t)t->T.tail_cells);
+    // A V-cycle from e = 0 on a tree whose leaves are all on the top level (of every
+    // domain) first smooths the top level, whose first half-sweep then needs no old
+    // values; every other value it reads is written by the cycle before it is read
+    // (restriction writes the parents and their ghosts, and the coarse grids).  Other
+    // cases start from explicitly zeroed fields.
+    bool same_top = true;
+    for (const HDomain &d : t->T.doms) same_top = same_top && d.top == t->T.nlev - 1;
+    const bool zs = !use_fmg && !t->T.refined && same_top && !jacobi(t) && t->prm.n_down > 0;
+    if (!zs) {
+        K<float>::zero(D.L, P.v, (size_t)(t->nb * t->nc));
+        K<float>::zero(D.L, P.vg, (size_t)(t->nb * t->ng));
+        K<float>::zero(D.L, P.tv, (size_t)t->T.tail_cells);
+    }
+    D.zero_first = zs;
     if (use_fmg) {
         D.fmg();
     } else {

@@ -90,8 +90,9 @@ struct Launch {
 // level; `mask` selects domains.
 template <typename T>
 struct K {
+    // zero: the other colour is known to be zero and is not read.
     static void gsrb(const Launch &L, const Plane<T> &P, int lev, int b0, int nb, int colour,
-                     uint64_t mask, bool var, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                     uint64_t mask, bool var, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool zero = false);
     static void ghost(const Launch &L, const Plane<T> &P, int b0, int nb, const int32_t *list,
                       int nlist, uint64_t mask, bool eps_field, bool cf_only);
     static void restrict_down(const Launch &L, const Plane<T> &P, int lev, int b0, int nb,

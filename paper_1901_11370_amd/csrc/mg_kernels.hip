@@ -301,7 +301,10 @@ __device__ __forceinline__ void push_ghosts(T *__restrict__ vg, const BlockCtx<D
 // serial part.  The parts of a block are nb workgroups apart: with nb a multiple of 8
 // they run on the same XCD (workgroups go round-robin over the 8 XCDs), so the repeated
 // staging reads hit that XCD's L2.
-template <typename T, int D, int BS, bool VAR, int SPLIT>
+// ZERO: the other colour and its ghosts are known to be zero (the first half-sweep of a
+// correction solve from e = 0, homogeneous boundary values), so they are not read, and
+// this colour's ghosts on physical faces are set to zero for the next half-sweep.
+template <typename T, int D, int BS, bool VAR, int SPLIT, bool ZERO>
 __global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev, int b0, int colour,
                                               uint64_t mask) {
     using g = G<D, BS>;
@@ -323,8 +326,10 @@ __global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev,
     // the block's tables; a block of a domain outside the mask leaves after staging
     Stager<T, 1, g::NH, 0, TPB> st_o;
     Stager<T, 2 * D, HF, g::NF, TPB> st_g;
-    st_o.load(P.v + b * g::NC + oc * g::NH);
-    st_g.load(P.vg + b * g::NG + oc * HF);
+    if (!ZERO) {
+        st_o.load(P.v + b * g::NC + oc * g::NH);
+        st_g.load(P.vg + b * g::NG + oc * HF);
+    }
     T fr[IT], er[VAR ? IT : 1];
 #pragma unroll
     for (int m = 0; m < IT; m++) fr[m] = P.f[b * g::NC + colour * g::NH + q0 + tid + m * TPB];
@@ -338,8 +343,24 @@ __global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev,
     }
     BlockCtx<D> cx;
     cx.load(tb, b, lev);
-    st_o.store(s_o);
-    st_g.store(s_g);
+    if (!ZERO) {
+        st_o.store(s_o);
+        st_g.store(s_g);
+    } else {
+        for (int q = tid; q < g::NH; q += TPB) s_o[q] = T(0);
+        for (int q = tid; q < NGH; q += TPB) s_g[q] = T(0);
+        // On a physical face the ghosts of this colour mirror cells of the other colour
+        // (zero), so with the homogeneous boundary values of a correction solve they are
+        // zero as well; the next half-sweep reads them.
+        unsigned phys = 0;
+#pragma unroll
+        for (int f = 0; f < 2 * D; f++) phys |= (cx.nbr[f] == -1 ? 1u : 0u) << f;
+        if (phys && q0 == 0)
+            for (int q = tid; q < NGH; q += TPB) {
+                const int f = q / HF;
+                if ((phys >> f) & 1) P.vg[b * g::NG + f * g::NF + colour * HF + (q - f * HF)] = T(0);
+            }
+    }
     if (VAR) {
         st_eo.store(s_eo);
         st_eg.store(s_eg);
@@ -2120,25 +2141,36 @@ __global__ void __launch_bounds__(256) k_scale(double *x, double a, int64_t n) {
 // With events, the launch records the kernel's own start and end (no extra packets).
 template <typename T>
 void K<T>::gsrb(const Launch &L, const Plane<T> &P, int lev, int b0, int nb, int colour, uint64_t mask,
-                bool var, hipEvent_t ev0, hipEvent_t ev1) {
+                bool var, hipEvent_t ev0, hipEvent_t ev1, bool zero) {
     if (nb <= 0) return;
     DISPATCH_DB(L, {
         constexpr int NH = G<D, BS>::NH;
         constexpr int TPB = NH < 256 ? NH : 256;
         constexpr int SP = NH / TPB >= 4 ? 4 : 1;
-        if (ev0) {
+        if (zero) {
+            // only the FP32 correction solves start from zero
+            if constexpr (sizeof(T) == 4) {
+                if (SP > 1 && nb <= 256) {
+                    if (var) k_gsrb<T, D, BS, true, SP, true><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+                    else k_gsrb<T, D, BS, false, SP, true><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+                } else {
+                    if (var) k_gsrb<T, D, BS, true, 1, true><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+                    else k_gsrb<T, D, BS, false, 1, true><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+                }
+            }
+        } else if (ev0) {
             if (var)
-                hipExtLaunchKernelGGL((k_gsrb<T, D, BS, true, 1>), dim3(nb), dim3(TPB), 0, L.stream, ev0, ev1, 0, P,
-                                      L.tb, lev, b0, colour, mask);
+                hipExtLaunchKernelGGL((k_gsrb<T, D, BS, true, 1, false>), dim3(nb), dim3(TPB), 0, L.stream, ev0, ev1, 0,
+                                      P, L.tb, lev, b0, colour, mask);
             else
-                hipExtLaunchKernelGGL((k_gsrb<T, D, BS, false, 1>), dim3(nb), dim3(TPB), 0, L.stream, ev0, ev1, 0, P,
-                                      L.tb, lev, b0, colour, mask);
+                hipExtLaunchKernelGGL((k_gsrb<T, D, BS, false, 1, false>), dim3(nb), dim3(TPB), 0, L.stream, ev0, ev1,
+                                      0, P, L.tb, lev, b0, colour, mask);
         } else if (SP > 1 && nb <= 256) {
-            if (var) k_gsrb<T, D, BS, true, SP><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
-            else k_gsrb<T, D, BS, false, SP><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+            if (var) k_gsrb<T, D, BS, true, SP, false><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+            else k_gsrb<T, D, BS, false, SP, false><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
         } else {
-            if (var) k_gsrb<T, D, BS, true, 1><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
-            else k_gsrb<T, D, BS, false, 1><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+            if (var) k_gsrb<T, D, BS, true, 1, false><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+            else k_gsrb<T, D, BS, false, 1, false><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
         }
     });
 }

@@ -358,3 +358,44 @@ def test_axisymmetric(case):
         _run(_axi_workload("axibig", [d]), "fvv", axisymmetric=1)
     else:
         _mixed_vs_reference_l(_axi_workload("aximix", [_axi_domain()]), 1e-8, 0.0, axisymmetric=1)
+
+
+# ------------------------------------------- mixed-form iterates, cycle by cycle
+@pytest.mark.parametrize("case", ["dirichlet_neumann_2d", "periodic_3d", "forest_equal", "forest_unequal", "amr"])
+def test_mixed_iterates_follow_fp64_cycles(case):
+    # a refinement step (FP32 cycle on the residual equation from e = 0, added to phi)
+    # equals one FAS cycle on phi up to FP32 rounding, so after FMG + 3 cycles the
+    # mixed iterate stays within ~1e-6 of the reference's FP64 iterate; an FP32 cycle
+    # that started from stale values instead of zero would leave the previous step's
+    # correction in it and miss that by orders of magnitude
+    if case == "dirichlet_neumann_2d":
+        dom = W.Domain(2, [128, 96], [0, 0], [1, 0.75], [W.DIRICHLET, W.NEUMANN, W.NEUMANN, W.DIRICHLET],
+                       [0.5, 0.2, -0.3, 1.0])
+        g = W.Gaussians(np.array([[0.4, 0.3]]), np.array([5.0]), np.array([0.1]))
+        w = W.Workload(case, [dom], bs=16, rhs=lambda i, lay: g(W.cell_centres(lay, dom)))
+    elif case == "periodic_3d":
+        w = W.config2(n=64)
+    elif case == "forest_equal":
+        w = W.config5(sizes=(48, 48))
+    elif case == "forest_unequal":
+        w = W.config5(sizes=(32, 64))
+    else:
+        w = W.config3(nested=False, base=32)
+    t = gpu_tree(w, precision=1)
+    refs = oracle_trees(w)
+    f, e = inputs(w, t)
+    if w.variable_eps:
+        t.set_eps(np.concatenate(e))
+        for o, ei in zip(refs, e):
+            o.set_eps(ei)
+    t.set_rhs(np.concatenate(f))
+    for o, fi in zip(refs, f):
+        o.set_rhs(fi)
+    t.fmg()
+    t.vcycle(3)
+    for o in refs:
+        o.fmg()
+        o.vcycle(3)
+    errs = [rel_err(p, o.get_phi(), case == "periodic_3d") for p, o in zip(split(t, t.get_phi()), refs)]
+    print(case, "mixed vs FP64 iterates", errs, flush=True)
+    assert max(errs) < 2e-6
