@@ -183,6 +183,11 @@ int mg_domain_residual_norms(mg_tree *t, double *max_rel, double *l2_rel);
  * the refinement is FGMRES(m) (flexible GMRES, restarted every m steps or when its
  * residual estimate falls by 1e-6; the true FP64 residual is checked at each restart);
  * one FP32 preconditioning solve counts as a cycle.  cycles_done may be NULL.
+ * The FP64 form with use_fmg_first runs its FMG cycle before the first norm check
+ * (the solve is meant to start from a guess that is not yet converged; this saves a
+ * residual evaluation); the mixed forms check first, since their first step needs the
+ * residual anyway.  Without FMG the norm is checked before any cycle, so a solve whose
+ * guess already meets rel_tol returns at once with 0 cycles.
  * Returns MG_ERR_NOT_CONVERGED if max_cycles is reached first. */
 int mg_solve(mg_tree *t, double rel_tol, int max_cycles, int use_fmg_first, int *cycles_done);
 /* Per-check record of the last mg_solve: relative residual and seconds since start. */

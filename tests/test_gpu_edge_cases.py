@@ -81,3 +81,45 @@ def test_laplace_with_boundary_values():
     t.vcycle(3)
     r1, _ = t.residual_norm()
     assert np.isfinite(r0) and r1 < 5e-3 * r0   # three cycles at about 0.1 each
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_zero_cycles_and_already_converged_solves(precision):
+    from paper_1901_11370_amd import mg
+    dom = W.Domain(3, [32, 32, 32], [0, 0, 0], [1, 1, 1], [W.DIRICHLET] * 6)
+    w = _gauss_workload("z", dom, 16)
+    t = gpu_tree(w, precision=precision)
+    f, _ = inputs(w, t)
+    t.set_rhs(f[0])
+    t.vcycle(0)
+    t.fmg(0)
+    assert np.all(t.get_phi() == 0.0)
+    # phi = 0: the relative residual is 1, so a tolerance above it needs no cycle
+    c, rc = t.solve(rel_tol=2.0, max_cycles=10, fmg_first=False)
+    assert (c, rc) == (0, mg.MG_OK) and np.all(t.get_phi() == 0.0)
+    for fmg in (False, True):
+        c, rc = t.solve(rel_tol=1e-10, max_cycles=0, fmg_first=fmg, raise_on_fail=False)
+        assert (c, rc) == (0, mg.MG_ERR_NOT_CONVERGED) and np.all(t.get_phi() == 0.0)
+    c, rc = t.solve(rel_tol=1e-10, max_cycles=40)
+    assert rc == mg.MG_OK and c > 0
+    phi = t.get_phi()
+    c, rc = t.solve(rel_tol=1e-10, max_cycles=40, fmg_first=False)
+    assert (c, rc) == (0, mg.MG_OK) and np.array_equal(t.get_phi(), phi)
+
+
+def test_zero_problem_stays_zero():
+    # f = 0 with homogeneous boundary values: phi = 0 is exact, the (absolute) residual
+    # is zero and every cycle leaves it there
+    from paper_1901_11370_amd import mg
+    dom = W.Domain(2, [64, 64], [0, 0], [1, 1], [W.DIRICHLET, W.NEUMANN, W.PERIODIC, W.PERIODIC])
+    w = W.Workload("zero", [dom], bs=16, rhs=lambda i, lay: np.zeros(len(lay)))
+    t = gpu_tree(w)
+    t.set_rhs(np.zeros(t.n_leaf))
+    t.fmg()
+    t.vcycle(2)
+    assert np.all(t.get_phi() == 0.0)
+    assert t.residual_norm() == (0.0, 0.0)
+    c, rc = t.solve(rel_tol=1e-10, max_cycles=5, fmg_first=False)
+    assert (c, rc) == (0, mg.MG_OK)
+    c, rc = t.solve(rel_tol=1e-10, max_cycles=5)   # the FP64 FMG runs before the first check
+    assert (c, rc) == (1, mg.MG_OK) and np.all(t.get_phi() == 0.0)

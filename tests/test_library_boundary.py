@@ -94,3 +94,39 @@ def test_invalid_arguments_are_rejected():
         mg.Tree([mg.Domain(2, (32, 32), (0, 0), (1, 1), [0] * 4)], bs=16, bind=False,
                 params=mg.default_params(axisymmetric=2))
     mg.Tree([mg.Domain(2, (32, 32), (0, 0), (1, 1), [1, 0, 2, 2])], bs=16, bind=False, params=axi)
+
+
+def test_degenerate_arguments_are_rejected_on_the_host():
+    import ctypes
+    from paper_1901_11370_amd import mg
+    L = mg._lib
+    p = mg.default_params()
+    out = ctypes.c_void_p()
+    d = mg.Domain(2, (32, 32), (0, 0), (1, 1), [0] * 4).to_c()
+    noref = mg.mg_refine_fn(0)
+    # no domains, a null domain array, a null result pointer, negative refinement
+    assert L.mg_tree_create((mg.mg_domain * 1)(d), 0, 16, 0, noref, None, ctypes.byref(p), ctypes.byref(out)) == mg.MG_ERR_ARG
+    assert L.mg_tree_create(None, 1, 16, 0, noref, None, ctypes.byref(p), ctypes.byref(out)) == mg.MG_ERR_ARG
+    assert L.mg_tree_create((mg.mg_domain * 1)(d), 1, 16, 0, noref, None, ctypes.byref(p), None) == mg.MG_ERR_ARG
+    assert L.mg_tree_create((mg.mg_domain * 1)(d), 1, 16, -1, noref, None, ctypes.byref(p), ctypes.byref(out)) == mg.MG_ERR_ARG
+    # more domains than a tree holds (64), domains of different dimension
+    many = (mg.mg_domain * 65)(*([d] * 65))
+    assert L.mg_tree_create(many, 65, 16, 0, noref, None, ctypes.byref(p), ctypes.byref(out)) == mg.MG_ERR_ARG
+    d3 = mg.Domain(3, (32, 32, 32), (0, 0, 0), (1, 1, 1), [0] * 6).to_c()
+    assert L.mg_tree_create((mg.mg_domain * 2)(d, d3), 2, 16, 0, noref, None, ctypes.byref(p),
+                            ctypes.byref(out)) == mg.MG_ERR_ARG
+    # an empty box, an inverted box, a non-positive cell count
+    bad = [mg.Domain(2, (32, 32), (0, 0), (0, 1), [0] * 4), mg.Domain(2, (32, 32), (1, 0), (0, 1), [0] * 4),
+           mg.Domain(2, (0, 32), (0, 0), (1, 1), [0] * 4)]
+    for b in bad:
+        with pytest.raises(mg.MGError):
+            mg.Tree([b], bs=16, bind=False)
+    # parameters out of range
+    for kw in ({"n_down": -1}, {"n_max_coarse": 0}, {"precision": 7}, {"ir_vcycles": 0}, {"graphs": 2},
+               {"smoother": 5}, {"jacobi_weight": 0.0}, {"jacobi_weight": 1.5}, {"helmholtz_lambda": -1.0}):
+        with pytest.raises(mg.MGError):
+            mg.Tree([mg.Domain(2, (32, 32), (0, 0), (1, 1), [0] * 4)], bs=16, bind=False,
+                    params=mg.default_params(**kw))
+    assert L.mg_default_params(None) == mg.MG_ERR_ARG
+    for st in range(-7, 1):
+        assert L.mg_strerror(st)
