@@ -40,6 +40,7 @@ struct mg_tree {
     double *d_stage = nullptr, *d_stage2 = nullptr;
     int32_t *d_steps = nullptr;
     double *d_partials = nullptr, *d_domnorms = nullptr;
+    double *d_hnorms = nullptr;      // device address of h_norms
     // FGMRES (mixed mode with krylov = m): V[m+1], Z[m] leaf vectors, inner-product
     // partials, dot results (3 sets), combination coefficients; pinned host copies
     double *d_kv = nullptr, *d_kz = nullptr, *d_kpart = nullptr, *d_kdots = nullptr, *d_ky = nullptr;
@@ -262,6 +263,7 @@ Launch launch(mg_tree *t, bool homogeneous) {
     L.coarse_steps = t->d_steps;
     L.partials = t->d_partials;
     L.dom_norms = t->d_domnorms;
+    L.host_norms = nullptr;
     L.tail_lds[0] = t->tail_lds[0];
     L.tail_lds[1] = t->tail_lds[1];
     return L;
@@ -516,9 +518,8 @@ void enq_residual(mg_tree *t, bool write_r32, bool copy_out) {
     // which every kernel keeps current; parents enter only through coarse-fine ghosts.
     if (t->T.refined) D.sync();
     launch_norm64(D.L, t->P64, (int)t->nleafblk, var(t), write_r32 ? t->P32.f : nullptr, nullptr);
+    if (copy_out) D.L.host_norms = t->d_hnorms;   // the reduction writes the pinned host buffer too
     launch_reduce_norms(D.L);
-    if (copy_out)
-        (void)hipMemcpyAsync(t->h_norms, t->d_domnorms, 4 * (size_t)t->T.ndom * 8, hipMemcpyDeviceToHost, t->stream);
 }
 
 // Waits for the stream and returns the norms copied by the last enq_residual.
@@ -643,9 +644,8 @@ void enq_add_residual(mg_tree *t, bool write_r32, bool copy_out) {
     }
     Driver<double> D = d64(t);
     launch_add_norm64(D.L, t->P64, t->P32.v, t->P32.vg, (int)t->nleafblk, var(t), write_r32 ? t->P32.f : nullptr);
+    if (copy_out) D.L.host_norms = t->d_hnorms;
     launch_reduce_norms(D.L);
-    if (copy_out)
-        (void)hipMemcpyAsync(t->h_norms, t->d_domnorms, 4 * (size_t)t->T.ndom * 8, hipMemcpyDeviceToHost, t->stream);
 }
 
 // ---- FGMRES refinement (mixed mode, krylov = m)
@@ -655,8 +655,8 @@ void enq_residual_vec(mg_tree *t, double *out) {
     Driver<double> D = d64(t);
     if (t->T.refined) D.sync();
     launch_norm64(D.L, t->P64, (int)t->nleafblk, var(t), nullptr, out);
+    D.L.host_norms = t->d_hnorms;
     launch_reduce_norms(D.L);
-    (void)hipMemcpyAsync(t->h_norms, t->d_domnorms, 4 * (size_t)t->T.ndom * 8, hipMemcpyDeviceToHost, t->stream);
 }
 
 // w = A z, A the composite operator with homogeneous boundary values; z is placed in
@@ -889,7 +889,10 @@ int mg_tree_bind(mg_tree *t, void *device_store, size_t bytes, void *hip_stream)
         prepare_kernels();
         HIP_OR_FAIL(t, hipStreamCreateWithFlags(&t->cap, hipStreamNonBlocking));
     }
-    if (!t->h_norms) HIP_OR_FAIL(t, hipHostMalloc((void **)&t->h_norms, 4 * (size_t)t->T.ndom * 8, hipHostMallocDefault));
+    if (!t->h_norms) {
+        HIP_OR_FAIL(t, hipHostMalloc((void **)&t->h_norms, 4 * (size_t)t->T.ndom * 8, hipHostMallocDefault));
+        HIP_OR_FAIL(t, hipHostGetDevicePointer((void **)&t->d_hnorms, t->h_norms, 0));
+    }
     if (!t->h_k && mixed(t) && t->prm.krylov > 0)
         HIP_OR_FAIL(t, hipHostMalloc((void **)&t->h_k, 4 * (size_t)(t->prm.krylov + 1) * 8, hipHostMallocDefault));
     t->store = (char *)device_store;

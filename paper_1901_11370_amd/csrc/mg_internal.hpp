@@ -82,6 +82,8 @@ struct Launch {
     int32_t *coarse_steps;      // [ndom] device: steps taken by the last coarsest solve
     double *partials;           // [nleaf_blocks][4] device scratch
     double *dom_norms;          // [ndom][4] device: max|r|, sum vol r^2, max|f|, sum vol f^2
+    double *host_norms;         // if set: device address of pinned host memory that receives
+                                // dom_norms as well (no separate copy)
     uint64_t tail_lds[2];       // domains whose coarse grids fit in the coarse solver's LDS:
                                 // [0] FP64 fields, [1] FP32 fields
 };

@@ -1896,7 +1896,8 @@ __global__ void __launch_bounds__(TPB) k_resid(Plane<double> P, DevTables tb, co
 }
 
 // Per-domain combination of the per-block partials (fixed order: deterministic).
-__global__ void __launch_bounds__(256) k_reduce_norms(DevTables tb, const double *partials, double *out) {
+__global__ void __launch_bounds__(256) k_reduce_norms(DevTables tb, const double *partials, double *out,
+                                                      double *host_out) {
     __shared__ double sm[4][256];
     const int dm = blockIdx.x;
     const int r0 = tb.leaf_first[dm], r1 = tb.leaf_first[dm + 1];
@@ -1920,7 +1921,10 @@ __global__ void __launch_bounds__(256) k_reduce_norms(DevTables tb, const double
         }
         __syncthreads();
     }
-    if (threadIdx.x < 4) out[4 * dm + threadIdx.x] = sm[threadIdx.x][0];
+    if (threadIdx.x < 4) {
+        out[4 * dm + threadIdx.x] = sm[threadIdx.x][0];
+        if (host_out) host_out[4 * dm + threadIdx.x] = sm[threadIdx.x][0];
+    }
 }
 
 // v64 += v32 on every leaf block (the FP64 update of iterative refinement), with the
@@ -2452,7 +2456,7 @@ void launch_divb_project(const Launch &L, const Plane<double> &P, double *Bd, do
 }
 
 void launch_reduce_norms(const Launch &L) {
-    k_reduce_norms<<<L.ndom, 256, 0, L.stream>>>(L.tb, L.partials, L.dom_norms);
+    k_reduce_norms<<<L.ndom, 256, 0, L.stream>>>(L.tb, L.partials, L.dom_norms, L.host_norms);
 }
 
 void launch_add_leaf(const Launch &L, double *v64, double *vg64, const float *v32, int nleafblk) {
