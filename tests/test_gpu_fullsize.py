@@ -87,3 +87,26 @@ def test_divb_clean_256_full_size():
     assert err <= 1e-11
     assert np.abs(Bg - Bn).max() <= 1e-9 * corr
     assert np.abs(eg - en).max() <= 1e-9 * corr * np.abs(B).max() + 4e-16 * np.abs(e).max()
+
+
+def test_amr_nested_full_size_residual_by_reference():
+    # the nested AMR tree of the amr-nested report line (115,867,648 leaf cells) solved to
+    # 1e-10 on the GPU; the reference solver builds the same tree, takes the GPU's phi and
+    # evaluates the composite residual itself (too large for the reference to run cycles)
+    import torch
+    w = W.config3(nested=True)
+    t = gpu_tree(w)
+    f, _ = inputs(w, t)
+    t.set_rhs(torch.from_numpy(f[0]).cuda())
+    cycles, rc = t.solve(rel_tol=1e-10, max_cycles=20)
+    g_rel, g_l2 = t.residual_norm()
+    phi = t.get_phi()
+    del t
+    o = oracle_trees(w)[0]
+    o.set_rhs(f[0])
+    o.set_phi(phi)
+    o_rel, o_l2 = o.residual_norm()
+    print("nested full size: cycles", cycles, "GPU residual", g_rel, g_l2, "reference on the GPU's phi", o_rel, o_l2,
+          flush=True)
+    assert rc == 0 and cycles <= 12
+    assert o_rel <= 1e-10 * 1.01 and abs(o_rel - g_rel) <= 1e-3 * g_rel and abs(o_l2 - g_l2) <= 1e-3 * g_l2
