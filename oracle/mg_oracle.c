@@ -16,7 +16,8 @@
 #include <string.h>
 
 #define OG_MAXLEV 40
-#define STALL 0.999   /* coarsest solve: a step must lower the residual below STALL x */
+#define STALL 0.999     /* coarsest solve: progress means a residual below STALL x the lowest so far */
+#define STALL_STEPS 8   /* coarsest solve: steps in a row without progress before it stops */
 #define NFIELD 5
 enum { F_V = 0, F_F = 1, F_VOLD = 2, F_R = 3, F_EPS = 4 };
 
@@ -750,11 +751,13 @@ static int all_periodic(const og_tree *t) {
 
 /* Coarsest grid (Sec. 2.4): smoothing steps until the max-norm residual is below the
  * absolute threshold or reduced by the relative factor, at most n_max steps, at least
- * one.  It also stops once a step, from the second on, lowers the residual by less
- * than 0.1%: at the rounding floor, and on a one-cell grid with Dirichlet faces, where
- * Gauss-Seidel with the ghost held fixed only alternates between two values (the
- * margin keeps that decision clear of rounding).  On a fully periodic domain the mean
- * of f is first removed on this level so that the singular system is consistent. */
+ * one.  It also stops once STALL_STEPS steps in a row have not brought the residual
+ * 0.1% below the lowest value reached so far: at the rounding floor, and on a one-cell
+ * grid with Dirichlet faces, where Gauss-Seidel with the ghost held fixed only
+ * alternates between two values (the margin keeps that decision clear of rounding).
+ * Several steps are allowed because the max-norm residual of a slowly converging grid
+ * can rise for a few steps before it falls.  On a fully periodic domain the mean of f
+ * is first removed on this level so that the singular system is consistent. */
 static void coarse_solve(og_tree *t) {
     const OLevel *L = &t->lev[0];
     if (all_periodic(t) && t->lambda == 0.0) {
@@ -770,15 +773,19 @@ static void coarse_solve(og_tree *t) {
             FOR_CELLS(t, 0, i, j, k) B->fld[F_F][pidx(t, 0, i, j, k)] -= mean;
         }
     }
-    double r0 = level_residual_max(t, 0), rprev = r0;
+    double r0 = level_residual_max(t, 0), best = r0;
     double target = t->abs_tol > t->rel_tol * r0 ? t->abs_tol : t->rel_tol * r0;
-    int k;
+    int k, since = 0;
     for (k = 1; k <= t->n_max; k++) {
         smooth_step(t, 0);
         double r = level_residual_max(t, 0);
         if (r <= target) break;
-        if (k >= 2 && r > STALL * rprev) break;
-        rprev = r;
+        if (r < STALL * best) {
+            best = r;
+            since = 0;
+        } else if (++since >= STALL_STEPS) {
+            break;
+        }
     }
     t->last_coarse_steps = k > t->n_max ? t->n_max : k;
 }

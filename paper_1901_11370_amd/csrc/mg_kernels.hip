@@ -16,9 +16,12 @@
 
 namespace mgx {
 
-// A coarsest-grid smoothing step must lower the max-norm residual below this factor
-// times the previous one, or the coarsest solve stops.
+// The coarsest solve stops once kStallSteps steps in a row have not lowered the
+// max-norm residual below kStall times the lowest value reached so far (the rounding
+// floor, or the two-value alternation of a one-cell Dirichlet grid; the residual of a
+// slowly converging grid may rise for a few steps before it falls).
 constexpr double kStall = 0.999;
+constexpr int kStallSteps = 8;
 
 // ---------------------------------------------------------------- geometry
 template <int D, int BS>
@@ -1248,10 +1251,9 @@ struct Tail {
     }
 
     // Coarsest grid: smoothing steps until the max-norm residual is <= max(abs,
-    // rel * initial), at most n_max, at least one; stop early once a step (from the
-    // second on) lowers it by less than 0.1% (rounding floor; the two-value
-    // alternation of a one-cell Dirichlet grid).  Fully periodic: remove the mean of
-    // f first.
+    // rel * initial), at most n_max, at least one; stop early once 8 steps in a row have
+    // not lowered it 0.1% below the lowest value so far (see kStall).  Fully periodic:
+    // remove the mean of f first.
     __device__ __forceinline__ int coarse_solve(const TailParams &tp) const {
         const TailLev g = lv[0];
         bool per = g.lam == 0.0;   // the regular Helmholtz operator needs no mean removal
@@ -1272,15 +1274,19 @@ struct Tail {
             __syncthreads();
         }
         const double r0 = resmax(0);
-        double rprev = r0;
+        double best = r0;
         const double target = fmax(tp.abs_tol, tp.rel_tol * r0);
-        int k;
+        int k, since = 0;
         for (k = 1; k <= tp.n_max; k++) {
             smooth(0);
             const double r = resmax(0);
             if (r <= target) break;
-            if (k >= 2 && r > kStall * rprev) break;
-            rprev = r;
+            if (r < kStall * best) {
+                best = r;
+                since = 0;
+            } else if (++since >= kStallSteps) {
+                break;
+            }
         }
         return k > tp.n_max ? tp.n_max : k;
     }

@@ -30,8 +30,8 @@ def _case(seed):
             k = int(rng.integers(0, 3))
             kinds += [W.PERIODIC, W.PERIODIC] if k == 2 else [int(rng.integers(0, 2)), int(rng.integers(0, 2))]
             vals += list(rng.uniform(-1, 1, size=2))
-        if all(k == W.PERIODIC for k in kinds) or all(k == W.NEUMANN for k in kinds):
-            kinds[0] = W.DIRICHLET      # keep the problem regular without a mean condition
+        if W.DIRICHLET not in kinds:
+            kinds[0] = W.DIRICHLET      # keep the problem regular (no constant null space)
             if kinds[1] == W.PERIODIC:
                 kinds[1] = W.NEUMANN
         doms.append(W.Domain(dim, n, list(lo), list(hi), kinds, vals))
@@ -83,3 +83,31 @@ def test_random_tree_matches_reference(seed):
     print(w.name, "dim", w.domains[0].dim, "bs", w.bs, "doms", len(w.domains), "leaf", t.n_leaf, params,
           "var", w.variable_eps, "err", max(errs), flush=True)
     assert max(errs) <= 1e-11
+
+
+@pytest.mark.parametrize("seed", range(0, 48, 2))
+def test_random_tree_mixed_solve_reaches_reference_solution(seed):
+    # the same trees in the mixed form, solved to 1e-10: FP64 refinement removes the FP32
+    # rounding of the corrections, so the solution is the reference's converged one
+    import torch
+    w, params = _case(seed)
+    t = gpu_tree(w, precision=1, **params)
+    refs = oracle_trees(w)
+    for o in refs:
+        if params.get("smoother") == 1:
+            o.set_smoother(o.JACOBI)
+        if "helmholtz_lambda" in params:
+            o.set_lambda(params["helmholtz_lambda"])
+    f, e = inputs(w, t)
+    if w.variable_eps:
+        t.set_eps(np.concatenate(e))
+        for o, ei in zip(refs, e):
+            o.set_eps(ei)
+    t.set_rhs(torch.from_numpy(np.concatenate(f)).cuda())
+    cycles, rc = t.solve(rel_tol=1e-10, max_cycles=60)
+    for o, fi in zip(refs, f):
+        o.set_rhs(fi)
+        o.solve(rel_tol=1e-12, max_cycles=120)
+    errs = [rel_err(p, o.get_phi()) for p, o in zip(split(t, t.get_phi()), refs)]
+    print(w.name, "mixed solve", cycles, "err", max(errs), flush=True)
+    assert rc == 0 and max(errs) <= 1e-8
