@@ -23,6 +23,16 @@ namespace mgx {
 constexpr double kStall = 0.999;
 constexpr int kStallSteps = 8;
 
+// Workgroups are dealt round-robin over the chip's 8 XCDs, each with its own L2.
+// Workgroup w of a launch over n blocks takes block xcd_block(w, n): XCD x gets a
+// contiguous run of the (Morton-ordered) blocks, so siblings that write halves of the
+// same cache lines of their parent block run under one L2 (the restriction).  A
+// bijection on [0, n).
+__device__ __forceinline__ int xcd_block(int w, int n) {
+    const int q = n >> 3, r = n & 7, x = w & 7;
+    return x * q + (x < r ? x : r) + (w >> 3);
+}
+
 // ---------------------------------------------------------------- geometry
 template <int D, int BS>
 struct G {
@@ -638,7 +648,7 @@ __global__ void __launch_bounds__(256) k_restrict(Plane<T> P, DevTables tb, int 
     constexpr bool FAS = MODE == RESTRICT_FAS;
     constexpr int IT = (NQ + TPB - 1) / TPB;
     __shared__ __align__(16) T s_v[FAS ? g::NC + g::NG : 4];
-    const int64_t b = b0 + blockIdx.x;
+    const int64_t b = b0 + xcd_block(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
     // tables first (independent loads): domain, parent, origin; the parent's
     // neighbours follow once the parent is known
@@ -927,15 +937,16 @@ __device__ __forceinline__ int tix(const TailLev &g, int i, int j, int k) {
     return g.off + (D == 3 ? (k + 1) * g.sz : 0) + (j + 1) * g.sy + (i + 1);
 }
 
-// Threads of the single-workgroup coarse solver (the variable-coefficient code needs
-// more registers).  Kernels use this constant rather than the block size at run time,
-// which the device library reads from memory at every use.
-template <bool VAR>
-constexpr int tail_threads() { return VAR ? 512 : 1024; }
+// Threads of the single-workgroup coarse solver (the variable-coefficient and 2D
+// forms need more registers; 2D tail grids are small).  Kernels use this constant
+// rather than the block size at run time, which the device library reads from memory
+// at every use.
+template <bool VAR, int D = 3>
+constexpr int tail_threads() { return VAR || D == 2 ? 512 : 1024; }
 
 template <typename T, int D, bool VAR>
 struct Tail {
-    static constexpr int NT = tail_threads<VAR>();
+    static constexpr int NT = tail_threads<VAR, D>();
     const TailLev *lv;         // [levels] in LDS
     TailBC bc;                 // boundary data (registers)
     double *red;               // reduction scratch in LDS, one slot per wave
@@ -1296,7 +1307,10 @@ struct Tail {
     __device__ __forceinline__ int run(const int *ops, int nops, const TailParams &tp) const {
         int steps = 0;
         for (int q = 0; q < nops; q++) {
-            const int kind = ops[q] >> 8, l = ops[q] & 255;
+            // the same word for every lane: kept in scalar registers (the level index
+            // would otherwise occupy a vector register across the whole operation)
+            const int op = __builtin_amdgcn_readfirstlane(ops[q]);
+            const int kind = op >> 8, l = op & 255;
             switch (kind) {
             case TOP_ENTER: enter(l); break;
             case TOP_DOWN:
@@ -1406,9 +1420,9 @@ __device__ __forceinline__ void tail_setup(const DevTables &tb, int dm, int nlev
 // The two forms are separate kernels: each holds one copy of the cycle code, which
 // keeps the instruction footprint within the instruction cache.
 template <typename T, int D, bool VAR, bool LDS>
-__global__ void __launch_bounds__(tail_threads<VAR>()) k_tail(Plane<T> P, DevTables tb, int mode, uint64_t mask,
+__global__ void __launch_bounds__((tail_threads<VAR, D>())) k_tail(Plane<T> P, DevTables tb, int mode, uint64_t mask,
                                                               TailParams tp, int32_t *steps_out, int lds_bytes) {
-    constexpr int NT = tail_threads<VAR>();
+    constexpr int NT = tail_threads<VAR, D>();
     extern __shared__ double smem[];
     __shared__ double red[16];
     __shared__ TailLev lvs[MAXLEV];
@@ -1438,13 +1452,42 @@ __global__ void __launch_bounds__(tail_threads<VAR>()) k_tail(Plane<T> P, DevTab
         T *sf = sv + n, *so = sf + n, *se = so + nold;
         __syncthreads();
         const TailLev &g = lvs[top];
-        for (int q = threadIdx.x; q < g.npad; q += NT) {
-            const T a = P.tv[first + g.off + q], c = P.tf[first + g.off + q];
-            sv[g.off + q] = a;
-            sf[g.off + q] = c;
+        // all loads of a batch are issued before the first LDS store, so the copy
+        // costs one memory round trip per batch rather than one per element
+        constexpr int CB = 8;
+        for (int q0 = 0; q0 < g.npad; q0 += CB * NT) {
+            T a[CB], c[CB];
+#pragma unroll
+            for (int r = 0; r < CB; r++) {
+                const int q = q0 + threadIdx.x + r * NT;
+                if (q < g.npad) {
+                    a[r] = P.tv[first + g.off + q];
+                    c[r] = P.tf[first + g.off + q];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < CB; r++) {
+                const int q = q0 + threadIdx.x + r * NT;
+                if (q < g.npad) {
+                    sv[g.off + q] = a[r];
+                    sf[g.off + q] = c[r];
+                }
+            }
         }
         if (VAR)
-            for (int q = threadIdx.x; q < n; q += NT) se[q] = P.teps[first + q];
+            for (int q0 = 0; q0 < n; q0 += CB * NT) {
+                T a[CB];
+#pragma unroll
+                for (int r = 0; r < CB; r++) {
+                    const int q = q0 + threadIdx.x + r * NT;
+                    if (q < n) a[r] = P.teps[first + q];
+                }
+#pragma unroll
+                for (int r = 0; r < CB; r++) {
+                    const int q = q0 + threadIdx.x + r * NT;
+                    if (q < n) se[q] = a[r];
+                }
+            }
         __syncthreads();
         const Tail<T, D, VAR> tl{lvs, bcs, red, sv, so, sf, VAR ? se : nullptr, P.tvold + first, top,
                                  P.tv2 ? P.tv2 + first : nullptr, tp.jacobi, tp.omega};
@@ -2263,7 +2306,7 @@ void prepare_kernels() {
 
 template <typename T, int D, bool VAR>
 static void launch_tail(const Launch &L, const Plane<T> &P, int mode, uint64_t mask, const TailParams &tp) {
-    constexpr int TPB = tail_threads<VAR>();
+    constexpr int TPB = tail_threads<VAR, D>();
     const uint64_t fit = L.tail_lds[sizeof(T) == 4 ? 1 : 0];
     if (mask & fit)
         k_tail<T, D, VAR, true><<<L.ndom, TPB, kTailLds, L.stream>>>(P, L.tb, mode, mask & fit, tp, L.coarse_steps,
