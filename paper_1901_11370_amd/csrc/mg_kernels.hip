@@ -908,6 +908,7 @@ struct TailLev {
     int rh;            // colour slots per row, (n[0] + 1) / 2
     int ghost_pass;    // periodic axis with an odd cell count
     float inv_rh, inv_n0, inv_n1;
+    int lg[3], lrh;    // log2 of n[a] and of rh where they are powers of two, else -1
     double h[3], ih2[3];
     double inv_den;    // 1 / (2 sum ih2 + lambda): the constant-coefficient diagonal
     double lam;        // Helmholtz term
@@ -929,6 +930,16 @@ __device__ __forceinline__ void divmod(int x, int d, float inv, int &q, int &r) 
     } else if (r >= d) {
         q++;
         r -= d;
+    }
+}
+
+// divmod by d = 2^lg with a shift and a mask (lg is the same in every lane).
+__device__ __forceinline__ void divmod2(int x, int d, float inv, int lg, int &q, int &r) {
+    if (lg >= 0) {
+        q = x >> lg;
+        r = x & (d - 1);
+    } else {
+        divmod(x, d, inv, q, r);
     }
 }
 
@@ -959,15 +970,15 @@ struct Tail {
 
     __device__ __forceinline__ void cell(const TailLev &g, int c, int &i, int &j, int &k) const {
         int r;
-        divmod(c, g.n[0], g.inv_n0, r, i);
-        if (D == 3) divmod(r, g.n[1], g.inv_n1, k, j);
+        divmod2(c, g.n[0], g.inv_n0, g.lg[0], r, i);
+        if (D == 3) divmod2(r, g.n[1], g.inv_n1, g.lg[1], k, j);
         else { j = r; k = 0; }
     }
     // Colour slot s of grid g -> cell of that colour; false past the end of a row.
     __device__ __forceinline__ bool slot(const TailLev &g, int s, int colour, int &i, int &j, int &k) const {
         int row, pos;
-        divmod(s, g.rh, g.inv_rh, row, pos);
-        if (D == 3) divmod(row, g.n[1], g.inv_n1, k, j);
+        divmod2(s, g.rh, g.inv_rh, g.lrh, row, pos);
+        if (D == 3) divmod2(row, g.n[1], g.inv_n1, g.lg[1], k, j);
         else { j = row; k = 0; }
         i = 2 * pos + ((j + k + colour) & 1);
         return i < g.n[0];
@@ -1012,8 +1023,9 @@ struct Tail {
                 const int side = q >= n1 * n2;
                 const int r = q - side * n1 * n2;
                 int c[3], in[3], op[3];
-                c[t1] = r % n1;
-                c[t2] = D == 3 ? r / n1 : 0;
+                const int l1 = g.lg[t1];
+                c[t1] = l1 >= 0 ? r & (n1 - 1) : r % n1;
+                c[t2] = D == 3 ? (l1 >= 0 ? r >> l1 : r / n1) : 0;
                 in[t1] = op[t1] = c[t1];
                 in[t2] = op[t2] = c[t2];
                 c[a] = side ? g.n[a] : -1;
@@ -1063,21 +1075,36 @@ struct Tail {
         const TailLev g = lv[lev];
         const bool gp = g.ghost_pass;
         const int ns = nslot(g);
-        for (int s = threadIdx.x; s < ns; s += NT) {
-            int i, j, k;
-            if (!slot(g, s, colour, i, j, k)) continue;
-            T w[6], nb[6];
-            stencil(g, i, j, k, w, nb);
-            T num = T(0), den = T(g.lam);
+        // Two slots per pass, every load of both issued before either store: a
+        // half-sweep reads only the other colour, and a physical ghost it writes is
+        // read only by the cell it mirrors, before that cell's update.
+        for (int s0 = threadIdx.x; s0 < ns; s0 += 2 * NT) {
+            int ii[2] = {0, 0}, jj[2] = {0, 0}, kk[2] = {0, 0}, oo[2] = {0, 0};
+            bool ok[2];
+            T fo[2], w[2][6], nb[2][6];
 #pragma unroll
-            for (int f = 0; f < 2 * D; f++) {
-                num += w[f] * nb[f];
-                den += w[f];
+            for (int u = 0; u < 2; u++) {
+                const int s = s0 + u * NT;
+                ok[u] = s < ns && slot(g, s, colour, ii[u], jj[u], kk[u]);
+                if (ok[u]) {
+                    oo[u] = tix<D>(g, ii[u], jj[u], kk[u]);
+                    fo[u] = tf[oo[u]];
+                    stencil(g, ii[u], jj[u], kk[u], w[u], nb[u]);
+                }
             }
-            const int o = tix<D>(g, i, j, k);
-            const T nv = VAR ? (num - tf[o]) / den : (num - tf[o]) * T(g.inv_den);
-            tv[o] = nv;
-            if (!gp) push(tv, g, i, j, k, nv, true);
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                if (!ok[u]) continue;
+                T num = T(0), den = T(g.lam);
+#pragma unroll
+                for (int f = 0; f < 2 * D; f++) {
+                    num += w[u][f] * nb[u][f];
+                    den += w[u][f];
+                }
+                const T nv = VAR ? (num - fo[u]) / den : (num - fo[u]) * T(g.inv_den);
+                tv[oo[u]] = nv;
+                if (!gp) push(tv, g, ii[u], jj[u], kk[u], nv, true);
+            }
         }
         __syncthreads();
         if (gp) {
@@ -1192,18 +1219,31 @@ struct Tail {
         return reduce_max(m);
     }
 
+    // dst = v on the padded grid g, two elements per pass (loads before stores; the
+    // arrays are distinct).  Separate call sites keep LDS and global stores apart.
+    __device__ __forceinline__ void copy_pad(T *dst, const TailLev &g) const {
+        for (int q = threadIdx.x; q < g.npad; q += 2 * NT) {
+            const bool two = q + NT < g.npad;
+            const T a = tv[g.off + q], b = two ? tv[g.off + q + NT] : T(0);
+            dst[g.off + q] = a;
+            if (two) dst[g.off + q + NT] = b;
+        }
+    }
     // v_old = v (ghosts included) and f += L v on grid lev (ghosts already valid).
     __device__ __forceinline__ void fas(int lev) const {
         const TailLev g = lv[lev];
-        if (tvold_top && lev == top) {
-            for (int q = threadIdx.x; q < g.npad; q += NT) tvold_top[g.off + q] = tv[g.off + q];
-        } else {
-            for (int q = threadIdx.x; q < g.npad; q += NT) tvold[g.off + q] = tv[g.off + q];
-        }
-        for (int c = threadIdx.x; c < g.ncell; c += NT) {
-            int i, j, k;
-            cell(g, c, i, j, k);
-            tf[tix<D>(g, i, j, k)] += Lv(g, i, j, k);
+        if (tvold_top && lev == top) copy_pad(tvold_top, g);
+        else copy_pad(tvold, g);
+        for (int c0 = threadIdx.x; c0 < g.ncell; c0 += 2 * NT) {
+            int ii[2] = {0, 0}, jj[2] = {0, 0}, kk[2] = {0, 0};
+            const bool two = c0 + NT < g.ncell;
+            cell(g, c0, ii[0], jj[0], kk[0]);
+            if (two) cell(g, c0 + NT, ii[1], jj[1], kk[1]);
+            const int o0 = tix<D>(g, ii[0], jj[0], kk[0]), o1 = tix<D>(g, ii[1], jj[1], kk[1]);
+            const T f0 = tf[o0], l0 = Lv(g, ii[0], jj[0], kk[0]);
+            const T f1 = two ? tf[o1] : T(0), l1 = two ? Lv(g, ii[1], jj[1], kk[1]) : T(0);
+            tf[o0] = f0 + l0;
+            if (two) tf[o1] = f1 + l1;
         }
         __syncthreads();
     }
@@ -1241,22 +1281,35 @@ struct Tail {
     // with the ghosts of lev pushed.
     __device__ __forceinline__ void correct(int lev) const {
         const TailLev gf = lv[lev], gc = lv[lev - 1];
-        for (int c = threadIdx.x; c < gf.ncell; c += NT) {
-            int i, j, k;
-            cell(gf, c, i, j, k);
-            const int p[3] = {i >> 1, j >> 1, k >> 1};
-            const int sg[3] = {(i & 1) ? 1 : -1, (j & 1) ? 1 : -1, (k & 1) ? 1 : -1};
-            const int o = tix<D>(gc, p[0], p[1], p[2]);
-            const T d0 = tv[o] - tvold[o];
-            const int st[3] = {1, gc.sy, gc.sz};
-            T dn[3];
+        // two fine cells per pass, every load of both before either store (the stores
+        // touch fine cells and their ghosts, the loads coarse cells and the cell itself)
+        for (int c0 = threadIdx.x; c0 < gf.ncell; c0 += 2 * NT) {
+            int ii[2] = {0, 0}, jj[2] = {0, 0}, kk[2] = {0, 0}, of[2];
+            T nv[2];
+            const bool two = c0 + NT < gf.ncell;
 #pragma unroll
-            for (int a = 0; a < D; a++) dn[a] = tv[o + sg[a] * st[a]] - tvold[o + sg[a] * st[a]];
-            const T corr = D == 2 ? T(0.25) * (T(2) * d0 + dn[0] + dn[1]) : T(0.25) * (d0 + dn[0] + dn[1] + dn[2]);
-            const int of = tix<D>(gf, i, j, k);
-            const T nv = tv[of] + corr;
-            tv[of] = nv;
-            push(tv, gf, i, j, k, nv, true);
+            for (int u = 0; u < 2; u++) {
+                if (u == 1 && !two) break;
+                cell(gf, c0 + u * NT, ii[u], jj[u], kk[u]);
+                const int i = ii[u], j = jj[u], k = kk[u];
+                const int p[3] = {i >> 1, j >> 1, k >> 1};
+                const int sg[3] = {(i & 1) ? 1 : -1, (j & 1) ? 1 : -1, (k & 1) ? 1 : -1};
+                const int o = tix<D>(gc, p[0], p[1], p[2]);
+                const T d0 = tv[o] - tvold[o];
+                const int st[3] = {1, gc.sy, gc.sz};
+                T dn[3];
+#pragma unroll
+                for (int a = 0; a < D; a++) dn[a] = tv[o + sg[a] * st[a]] - tvold[o + sg[a] * st[a]];
+                const T corr = D == 2 ? T(0.25) * (T(2) * d0 + dn[0] + dn[1]) : T(0.25) * (d0 + dn[0] + dn[1] + dn[2]);
+                of[u] = tix<D>(gf, i, j, k);
+                nv[u] = tv[of[u]] + corr;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                if (u == 1 && !two) break;
+                tv[of[u]] = nv[u];
+                push(tv, gf, ii[u], jj[u], kk[u], nv[u], true);
+            }
         }
         __syncthreads();
     }
@@ -1391,6 +1444,8 @@ __device__ __forceinline__ void tail_setup(const DevTables &tb, int dm, int nlev
         g.inv_rh = 1.0f / (float)g.rh;
         g.inv_n0 = 1.0f / (float)g.n[0];
         g.inv_n1 = 1.0f / (float)g.n[1];
+        for (int a = 0; a < 3; a++) g.lg[a] = (g.n[a] & (g.n[a] - 1)) == 0 ? __builtin_ctz(g.n[a]) : -1;
+        g.lrh = (g.rh & (g.rh - 1)) == 0 ? __builtin_ctz(g.rh) : -1;
         g.ghost_pass = 0;
         for (int a = 0; a < dim; a++) {
             if (tb.bck[6 * dm + 2 * a] == MG_BC_PERIODIC && (g.n[a] & 1)) g.ghost_pass = 1;
@@ -1491,14 +1546,14 @@ __global__ void __launch_bounds__((tail_threads<VAR, D>())) k_tail(Plane<T> P, D
         __syncthreads();
         const Tail<T, D, VAR> tl{lvs, bcs, red, sv, so, sf, VAR ? se : nullptr, P.tvold + first, top,
                                  P.tv2 ? P.tv2 + first : nullptr, tp.jacobi, tp.omega};
-        steps = tl.run(ops, nops, tp);
+        steps = tl.run(ops, __builtin_amdgcn_readfirstlane(nops), tp);
         for (int q = threadIdx.x; q < g.npad; q += NT) P.tv[first + g.off + q] = sv[g.off + q];
     } else {
         __syncthreads();
         const Tail<T, D, VAR> tl{lvs, bcs, red, P.tv + first, P.tvold + first, P.tf + first,
                                  VAR ? P.teps + first : nullptr, nullptr, top,
                                  P.tv2 ? P.tv2 + first : nullptr, tp.jacobi, tp.omega};
-        steps = tl.run(ops, nops, tp);
+        steps = tl.run(ops, __builtin_amdgcn_readfirstlane(nops), tp);
     }
     if (threadIdx.x == 0) steps_out[dm] = steps;
 }
