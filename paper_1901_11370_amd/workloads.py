@@ -324,3 +324,20 @@ def divb_periodic(n: int, dim: int = 3) -> Workload:
     """Periodic box [-1,1]^dim of n^dim cells in 16^dim blocks for the cleaning runs."""
     dom = Domain(dim, [n] * dim, [-1.0] * dim, [1.0] * dim, [PERIODIC] * (2 * dim))
     return Workload(f"divb_periodic{dim}d_{n}", [dom], bs=16)
+
+
+def freespace_gauss(sizes: Sequence[int] = (64,), sigma: float = 0.1, bs: int = 16,
+                    offsets: Optional[Sequence[Sequence[float]]] = None) -> Workload:
+    """The free-space test of Sec. 3.2: unit cubes centred at the origin, each of n^3
+    cells in bs^3 blocks, homogeneous Dirichlet faces (the free-space values are folded
+    into the right-hand side), f = -exp(-|r - r0|^2 / sigma^2) / (sigma^3 pi^(3/2)) with
+    r0 = 0 or the given per-domain offsets.  Several sizes make a forest of independent
+    problems."""
+    doms = [Domain(3, [n] * 3, [-0.5] * 3, [0.5] * 3, [DIRICHLET] * 6) for n in sizes]
+    r0s = [tuple(o) for o in offsets] if offsets is not None else [(0.0, 0.0, 0.0)] * len(doms)
+
+    def rhs(i, lay):
+        x = cell_centres(lay, doms[i]) - np.asarray(r0s[i])
+        return -np.exp(-np.sum(x * x, axis=1) / sigma ** 2) / (sigma ** 3 * np.pi ** 1.5)
+    name = "freespace_gauss_" + "_".join(str(n) for n in sizes)
+    return Workload(name, doms, bs=bs, rhs=rhs, note=f"sigma={sigma}; centres {r0s}")
