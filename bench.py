@@ -40,7 +40,7 @@ def _args():
     p.add_argument("--cpu-sample-cycles", type=int, default=1, help="V-cycles after the FMG in the CPU sample")
     p.add_argument("--workload", default="periodic256",
                    choices=["periodic256", "dirichlet2d", "amr-literal", "amr-nested", "varcoef-nested", "batch",
-                            "tree-build", "paper-scaling", "convergence", "helmholtz", "divb-clean"],
+                            "tree-build", "paper-scaling", "convergence", "helmholtz", "divb-clean", "freespace"],
                    help="periodic256 is the benchmark line; the others print report lines")
     p.add_argument("--max-cycles", type=int, default=60)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -361,6 +361,53 @@ def report(a):
         out["value"] = out["fp64_order4"]["cells_per_s"]
         out["ms_per_step"] = out["fp64_order4"]["ms_per_clean"]
         out["note"] = "ms_per_clean includes restoring B and e from a copy (about 0.15 ms)"
+        print(json.dumps(out), flush=True)
+        return
+    if a.workload == "freespace":
+        # free-space boundaries (Sec. 2.8) on the paper's test (Sec. 3.2: Gaussian source,
+        # sigma 0.1, unit cube centred at the origin), 256^3 leaf cells: boundary values
+        # from the charges 2^k coarser, folded into f, then FMG + V-cycles to the tolerance
+        w = W.freespace_gauss((a.n,))
+        out = dict(base, metric="free-space boundary values + solve time", dtype="f64 and mixed",
+                   config={"workload": f"freespace_gauss_{a.n}^3_sigma0.1_to_{a.tol:g}"})
+        for k in (2, 1):
+            for prec, key in ((mg.MG_FP64, "fp64"), (mg.MG_MIXED, "mixed")):
+                t = _tree_of(w, prec, mg)
+                lay = t.leaf_layout()
+                f = torch.from_numpy(w.rhs(0, lay[:, 1:])).cuda()
+                z = torch.zeros(t.n_leaf, dtype=torch.float64, device="cuda")
+
+                def bc():
+                    t.set_rhs(f)
+                    t.freespace_bc(k)
+
+                def run():
+                    bc()
+                    t.set_phi(z)
+                    return t.solve(rel_tol=a.tol, max_cycles=MAX_CYCLES, fmg_first=True, raise_on_fail=False)
+
+                dt, cyc, rcs, _ = timed(t, None, None, a.tol, a.steps, a.warmup, fn=run)
+                for _ in range(a.warmup):
+                    bc()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(a.steps):
+                    bc()
+                torch.cuda.synchronize()
+                ms_bc = (time.perf_counter() - t0) / a.steps * 1e3
+                e = t.get_phi() - w.target(0, lay[:, 1:])
+                nc = a.n >> k
+                pairs = 6 * (nc + 2) ** 2 * nc ** 3
+                res = {"ms_total": dt * 1e3, "ms_boundary_values": ms_bc, "cycles": cyc[-1],
+                       "converged": all(rc == 0 for rc in rcs), "coarse_cells": nc ** 3,
+                       "plane_points": 6 * (nc + 2) ** 2, "pair_terms_per_s": pairs / (ms_bc * 1e-3),
+                       "err_l2": float(np.sqrt(np.mean(e * e))), "err_max": float(np.max(np.abs(e)))}
+                out[f"{key}_coarsen{k}"] = res
+                del t
+        out["value"] = a.n ** 3 / (out["fp64_coarsen2"]["ms_total"] * 1e-3)
+        out["ms_per_step"] = out["fp64_coarsen2"]["ms_total"]
+        out["note"] = ("ms_boundary_values includes setting f (a device copy); pair terms: plane points x "
+                       "coarse cells of the direct Green's-function sum")
         print(json.dumps(out), flush=True)
         return
     if a.workload == "tree-build":

@@ -223,6 +223,29 @@ int mg_face_gradient(mg_tree *t, const double *leaf_phi, const double *leaf_lamb
 int mg_divb_rhs(mg_tree *t, const double *leaf_B, int order, int on_device);
 int mg_divb_project(mg_tree *t, double *leaf_B, double *leaf_e, int on_device);
 
+/* Free-space boundary conditions (Sec. 2.8; test problem of Sec. 3.2): phi -> 0 at
+ * infinity for the Laplacian.  The current right-hand side (mg_set_rhs) is restricted
+ * to the uniform level 2^coarsen leaf cells coarser (the mean of each coarse cell's
+ * leaf cells); the free-space potential of that grid, each coarse cell a point charge
+ * q = mean(f) h_c^3 at its centre, phi(x) = -(1/4 pi) sum q / |x - x_c|, is summed at
+ * the coarse face centres of the six boundary planes (plus one ghost position beyond
+ * each edge); the planes are interpolated linearly to the centres of the leaf faces.
+ * These Dirichlet values a enter the right-hand side in place, f -= 2 a / h^2 for each
+ * boundary face of a cell (the Dirichlet ghost 2a - phi_b of Sec. 2.6), so that a solve
+ * with the tree's homogeneous Dirichlet faces solves the free-space problem.  Calling
+ * it twice folds the values twice; mg_set_rhs restores a plain right-hand side.
+ *
+ * Requirements (MG_ERR_ARG otherwise): 3D, no refinement, eps = 1, lambda = 0,
+ * every face of every domain Dirichlet with value 0, 1 <= coarsen with 2^coarsen <=
+ * block size, at most 2048 coarse cells along x.  Domains are independent problems.
+ * bvals (may be NULL; host memory, or device memory with on_device = 1) receives the
+ * boundary values: domain by domain, face by face (-x, +x, -y, +y, -z, +z), each face
+ * over its leaf cells with the lower in-plane axis fastest; mg_freespace_values gives
+ * the count.  Uses the library's staging buffers as scratch and synchronises the
+ * stream. */
+int mg_freespace_bc(mg_tree *t, int coarsen, double *bvals, int on_device);
+int mg_freespace_values(const mg_tree *t, int64_t *n_values);
+
 /* Kernel timing: when enabled, HIP events bracket every launch of the smoothing
  * kernel on the finest level (on the bound stream); mg_profile_read returns the
  * number of such launches and their total milliseconds since enabling. */

@@ -1267,6 +1267,90 @@ int mg_divb_project(mg_tree *t, double *leaf_B, double *leaf_e, int on_device) {
     return MG_OK;
 }
 
+int mg_freespace_bc(mg_tree *t, int coarsen, double *bvals, int on_device) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    const HostTree &T = t->T;
+    if (T.dim != 3) return fail(t, MG_ERR_ARG, "free-space boundaries are three-dimensional");
+    if (T.refined) return fail(t, MG_ERR_ARG, "free-space boundaries need a tree without refinement");
+    if (var(t) || t->prm.helmholtz_lambda != 0.0 || t->prm.axisymmetric)
+        return fail(t, MG_ERR_ARG, "free-space boundaries need the plain Laplacian (eps = 1, lambda = 0)");
+    if (coarsen < 1 || (1 << coarsen) > T.bs)
+        return fail(t, MG_ERR_ARG, "coarsen must satisfy 1 <= coarsen and 2^coarsen <= block size");
+    const int c = 1 << coarsen;
+    std::vector<FsDom> fd(T.ndom);
+    int64_t qtot = 0, ptot = 0, btot = 0;
+    int max_pts = 0;
+    for (int i = 0; i < T.ndom; i++) {
+        const mg_domain &d = T.doms[i].d;
+        for (int f = 0; f < 6; f++)
+            if (d.bc.kind[f] != MG_BC_DIRICHLET || d.bc.value[f] != 0.0)
+                return fail(t, MG_ERR_ARG, "free-space boundaries need homogeneous Dirichlet faces");
+        FsDom &g = fd[i];
+        std::memset(&g, 0, sizeof g);
+        for (int a = 0; a < 3; a++) {
+            g.lo[a] = d.lo[a];
+            g.hi[a] = d.hi[a];
+            g.n[a] = d.base_cells[a];
+            g.nc[a] = d.base_cells[a] / c;
+            g.h[a] = (d.hi[a] - d.lo[a]) / d.base_cells[a];
+            g.hc[a] = g.h[a] * c;
+        }
+        if (g.nc[0] > 2048) return fail(t, MG_ERR_ARG, "more than 2048 coarse cells along x");
+        g.qoff = qtot;
+        g.poff = ptot;
+        g.boff = btot;
+        int64_t pp = 0, bb = 0;
+        for (int f = 0; f < 6; f++) {
+            const int a = f / 2, t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+            g.pofs[f] = pp;
+            g.bofs[f] = bb;
+            pp += (int64_t)(g.nc[t1] + 2) * (g.nc[t2] + 2);
+            bb += (int64_t)g.n[t1] * g.n[t2];
+        }
+        g.npts = (int32_t)pp;
+        max_pts = std::max(max_pts, g.npts);
+        qtot += (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
+        ptot += pp;
+        btot += bb;
+    }
+    // scratch in the two leaf-sized staging buffers: charges and the domain table in the
+    // first; planes, staged boundary values and the slices' partial sums in the second
+    const int64_t n = T.nleaf_cells;
+    const int64_t fd_words = ((int64_t)sizeof(FsDom) * T.ndom + 7) / 8;
+    // (the staging room for host output is always set aside, so that the slice count,
+    // and with it the summation order, does not depend on where the values go)
+    const int64_t bstage = btot;
+    const int64_t room = n - ptot - bstage;
+    if (qtot + fd_words > n || room < ptot) return fail(t, MG_ERR_ARG, "grids too small for the free-space scratch");
+    const int wgs = (int)((max_pts + 255) / 256) * T.ndom;
+    int slices = std::max(1, (1024 + wgs - 1) / wgs);
+    slices = (int)std::min<int64_t>(std::min(slices, 64), room / ptot);
+    double *q = t->d_stage;
+    FsDom *dfd = reinterpret_cast<FsDom *>(t->d_stage + qtot);
+    double *pl = t->d_stage2, *bst = t->d_stage2 + ptot, *partial = t->d_stage2 + ptot + bstage;
+    HIP_OR_FAIL(t, hipMemcpyAsync(dfd, fd.data(), sizeof(FsDom) * T.ndom, hipMemcpyHostToDevice, t->stream));
+    double *bv = bvals ? (on_device ? bvals : bst) : nullptr;
+    launch_freespace(launch(t, false), t->P64.f, dfd, T.ndom, max_pts, ptot, c, slices, q, partial, pl, bv,
+                     (int)t->nleafblk);
+    if ((rc = check_launch(t))) return rc;
+    if (bvals && !on_device)
+        HIP_OR_FAIL(t, hipMemcpyAsync(bvals, bst, (size_t)btot * 8, hipMemcpyDeviceToHost, t->stream));
+    HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));   // the domain table lives on this stack
+    return MG_OK;
+}
+
+int mg_freespace_values(const mg_tree *t, int64_t *n_values) {
+    if (!t || !n_values) return MG_ERR_ARG;
+    int64_t b = 0;
+    for (int i = 0; i < t->T.ndom; i++) {
+        const int32_t *m = t->T.doms[i].d.base_cells;
+        b += 2 * ((int64_t)m[0] * m[1] + (int64_t)m[1] * m[2] + (int64_t)m[0] * m[2]);
+    }
+    *n_values = t->T.dim == 3 ? b : 0;
+    return MG_OK;
+}
+
 int mg_profile_enable(mg_tree *t, int on) {
     if (!t) return MG_ERR_ARG;
     t->prof = on != 0;

@@ -161,6 +161,21 @@ void launch_divb(const Launch &L, const double *Bd, double *out, int d, bool acc
 // B_d -= dphi/dx_d (second-order central differences of P.v with its ghosts); if e is
 // set, e += (B_new^2 - B_old^2) / 2.
 void launch_divb_project(const Launch &L, const Plane<double> &P, double *Bd, double *e, int d, int64_t nleaf_cells);
+// Free-space boundaries (Sec. 2.8) on a 3D tree without refinement: per-domain geometry
+// of the coarse charge grid, its boundary planes and the leaf boundary values.
+struct FsDom {
+    double lo[3], hi[3], h[3], hc[3];   // box, leaf and coarse spacing
+    int32_t n[3], nc[3];                // leaf and coarse cells per axis
+    int64_t qoff, poff, boff;           // this domain's charges, plane points, boundary values
+    int64_t pofs[6], bofs[6];           // face offsets within the domain's planes / values
+    int32_t npts;                       // plane points of the domain
+    int32_t pad;
+};
+// Charges -> plane potentials (S slices of the charge rows, summed in a fixed order)
+// -> boundary values folded into f (leaf blocks, in place); bv (may be null) receives
+// the values.  partial holds S * total plane points.
+void launch_freespace(const Launch &L, double *f, const FsDom *fd, int ndom, int max_pts, int64_t tot_pts,
+                      int c, int slices, double *q, double *partial, double *pl, double *bv, int nleafblk);
 void launch_face_gradient(const Launch &L, const Plane<double> &P, const double *lam_blocks,
                           const double *lam_g, double *out_leaf, int nleafblk);
 

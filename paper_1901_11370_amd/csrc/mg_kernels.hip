@@ -2152,6 +2152,144 @@ __global__ void __launch_bounds__(256) k_divb_project(Plane<double> P, double *_
     if (e) e[id] += 0.5 * (bn * bn - bo * bo);
 }
 
+// ------------------------------------------------------ free-space boundaries
+// Sec. 2.8: the right-hand side restricted to a uniform level c = 2^k leaf cells
+// coarser, the free-space potential of that grid on the six boundary planes (coarse
+// face centres plus one ghost position on each side of a row), linear interpolation of
+// the planes to the leaf faces, and those Dirichlet values folded into the right-hand
+// side of a solve with homogeneous faces: f -= 2 a / h^2 per boundary face (the
+// Dirichlet ghost 2a - phi_b of Sec. 2.6).  The potential of the coarse grid is summed
+// directly, each coarse cell a point charge q = mean(f) h_c^3 at its centre.
+
+// One workgroup per leaf block: the charges of the coarse cells inside it (c <= BS).
+template <int BS>
+__global__ void __launch_bounds__(256) k_fs_charge(const double *__restrict__ f, DevTables tb,
+                                                   const FsDom *__restrict__ fd, int c, double *__restrict__ q) {
+    using g = G<3, BS>;
+    const int64_t b = tb.leaf_blk[blockIdx.x];
+    const FsDom d = fd[tb.dom[b]];
+    const int m = BS / c;
+    const int ox = tb.org[3 * b] / c, oy = tb.org[3 * b + 1] / c, oz = tb.org[3 * b + 2] / c;
+    const double vol = d.hc[0] * d.hc[1] * d.hc[2];
+    const double inv = 1.0 / (double)(c * c * c);
+    for (int t = threadIdx.x; t < m * m * m; t += 256) {
+        const int I = t % m, J = (t / m) % m, K = t / (m * m);
+        double s = 0.0;
+        for (int kk = 0; kk < c; kk++)
+            for (int jj = 0; jj < c; jj++)
+                for (int ii = 0; ii < c; ii++) s += f[b * g::NC + g::in(I * c + ii, J * c + jj, K * c + kk)];
+        q[d.qoff + ((int64_t)(oz + K) * d.nc[1] + (oy + J)) * d.nc[0] + (ox + I)] = s * inv * vol;
+    }
+}
+
+// Partial sums sum_c q_c / |x - x_c| at the plane points of domain blockIdx.y over the
+// charge rows of slice blockIdx.z; the rows pass through LDS in chunks and every thread
+// adds them in index order.
+constexpr int kFsChunk = 2048;
+__global__ void __launch_bounds__(256) k_fs_plane(const double *__restrict__ q, const FsDom *__restrict__ fd,
+                                                  double *__restrict__ partial, int64_t tot_pts, int slices) {
+    __shared__ double sq[kFsChunk];
+    const FsDom *dp = fd + blockIdx.y;
+    const int npts = dp->npts;
+    if ((int)blockIdx.x * 256 >= npts) return;   // the whole workgroup is past this domain's points
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const bool live = p < npts;
+    double px = 0.0, py = 0.0, pz = 0.0;
+    if (live) {
+        int r = p, face = 0;
+        while (face < 5 && r >= (int)(dp->pofs[face + 1] - dp->pofs[face])) {
+            r -= (int)(dp->pofs[face + 1] - dp->pofs[face]);
+            face++;
+        }
+        const int a = face >> 1, t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;   // in-plane axes t1 < t2
+        const int m1 = dp->nc[t1] + 2;
+        const int i1 = r % m1 - 1, i2 = r / m1 - 1;
+        const double c1 = dp->lo[t1] + (i1 + 0.5) * dp->hc[t1];
+        const double c2 = dp->lo[t2] + (i2 + 0.5) * dp->hc[t2];
+        const double ca = (face & 1) ? dp->hi[a] : dp->lo[a];
+        px = a == 0 ? ca : c1;
+        py = a == 1 ? ca : (a == 0 ? c1 : c2);
+        pz = a == 2 ? ca : c2;
+    }
+    const int nx = dp->nc[0], ny = dp->nc[1], rows = dp->nc[1] * dp->nc[2];
+    const double lo0 = dp->lo[0], lo1 = dp->lo[1], lo2 = dp->lo[2];
+    const double hc0 = dp->hc[0], hc1 = dp->hc[1], hc2 = dp->hc[2];
+    const int64_t qoff = dp->qoff, poff = dp->poff;
+    const int r0 = (int)((int64_t)rows * blockIdx.z / slices), r1 = (int)((int64_t)rows * (blockIdx.z + 1) / slices);
+    const int rc = kFsChunk / nx;                   // rows per chunk (nx <= kFsChunk)
+    double s = 0.0;
+    for (int c0 = r0; c0 < r1; c0 += rc) {
+        const int nr = min(rc, r1 - c0);
+        __syncthreads();
+        for (int u = threadIdx.x; u < nr * nx; u += 256) sq[u] = q[qoff + (int64_t)c0 * nx + u];
+        __syncthreads();
+        if (live) {
+            for (int rr = 0; rr < nr; rr++) {
+                const int row = c0 + rr, J = row % ny, K = row / ny;
+                const double dy = py - (lo1 + (J + 0.5) * hc1);
+                const double dz = pz - (lo2 + (K + 0.5) * hc2);
+                const double dyz = dy * dy + dz * dz;
+                for (int I = 0; I < nx; I++) {
+                    const double dx = px - (lo0 + (I + 0.5) * hc0);
+                    s += sq[rr * nx + I] * rsqrt(dx * dx + dyz);
+                }
+            }
+        }
+    }
+    if (live) partial[blockIdx.z * tot_pts + poff + p] = s;
+}
+
+// The slices' partial sums in slice order, times -1 / (4 pi).
+__global__ void __launch_bounds__(256) k_fs_sum(const double *__restrict__ partial, double *__restrict__ pl,
+                                                int64_t tot_pts, int slices) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= tot_pts) return;
+    double s = 0.0;
+    for (int z = 0; z < slices; z++) s += partial[z * tot_pts + i];
+    pl[i] = -s / (4.0 * M_PI);
+}
+
+// One workgroup per leaf block on a domain face: the boundary values of its face cells
+// by linear interpolation of the plane, folded into f face by face (x-, x+, ..., z+);
+// bv (may be null) receives them in the face-by-face order of the public interface.
+template <int BS>
+__global__ void __launch_bounds__(256) k_fs_fold(double *__restrict__ f, DevTables tb, const FsDom *__restrict__ fd,
+                                                 int c, const double *__restrict__ pl, double *__restrict__ bv) {
+    using g = G<3, BS>;
+    const int64_t b = tb.leaf_blk[blockIdx.x];
+    unsigned phys = 0;
+#pragma unroll
+    for (int face = 0; face < 6; face++) phys |= (tb.nbr[6 * b + face] == -1 ? 1u : 0u) << face;
+    if (!phys) return;
+    const FsDom d = fd[tb.dom[b]];
+    const int o[3] = {tb.org[3 * b], tb.org[3 * b + 1], tb.org[3 * b + 2]};
+    for (int t = threadIdx.x; t < g::NC; t += 256) {
+        const int cc[3] = {t % BS, (t / BS) % BS, t / (BS * BS)};
+        const int64_t at = b * g::NC + g::in(cc[0], cc[1], cc[2]);
+        double fv = 0.0;
+        bool any = false;
+#pragma unroll
+        for (int face = 0; face < 6; face++) {
+            const int a = face >> 1, t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+            if (!((phys >> face) & 1) || cc[a] != ((face & 1) ? BS - 1 : 0)) continue;
+            if (!any) fv = f[at];
+            any = true;
+            const int j1 = o[t1] + cc[t1], j2 = o[t2] + cc[t2];
+            const double u1 = (j1 + 0.5) * d.h[t1] / d.hc[t1] - 0.5, u2 = (j2 + 0.5) * d.h[t2] / d.hc[t2] - 0.5;
+            const int i1 = (int)floor(u1), i2 = (int)floor(u2);
+            const double w1 = u1 - i1, w2 = u2 - i2;
+            const int m1 = d.nc[t1] + 2;
+            const double *P = pl + d.poff + d.pofs[face];
+            const double p00 = P[(i2 + 1) * m1 + i1 + 1], p01 = P[(i2 + 1) * m1 + i1 + 2];
+            const double p10 = P[(i2 + 2) * m1 + i1 + 1], p11 = P[(i2 + 2) * m1 + i1 + 2];
+            const double av = (1 - w2) * ((1 - w1) * p00 + w1 * p01) + w2 * ((1 - w1) * p10 + w1 * p11);
+            if (bv) bv[d.boff + d.bofs[face] + (int64_t)j2 * d.n[t1] + j1] = av;
+            fv -= 2.0 * av / (d.h[a] * d.h[a]);
+        }
+        if (any) f[at] = fv;
+    }
+}
+
 // ================================================================ launchers
 #define HIPCHK(x) (x)
 
@@ -2557,6 +2695,24 @@ void launch_divb_project(const Launch &L, const Plane<double> &P, double *Bd, do
     if (nleaf_cells <= 0) return;
     const unsigned grid = (unsigned)((nleaf_cells + 255) / 256);
     DISPATCH_DB(L, { k_divb_project<D, BS><<<grid, 256, 0, L.stream>>>(P, Bd, e, L.tb, d, nleaf_cells); });
+}
+
+void launch_freespace(const Launch &L, double *f, const FsDom *fd, int ndom, int max_pts, int64_t tot_pts,
+                      int c, int slices, double *q, double *partial, double *pl, double *bv, int nleafblk) {
+    if (nleafblk <= 0 || tot_pts <= 0) return;
+    switch (L.bs) {
+    case 16: k_fs_charge<16><<<nleafblk, 256, 0, L.stream>>>(f, L.tb, fd, c, q); break;
+    case 8: k_fs_charge<8><<<nleafblk, 256, 0, L.stream>>>(f, L.tb, fd, c, q); break;
+    default: k_fs_charge<4><<<nleafblk, 256, 0, L.stream>>>(f, L.tb, fd, c, q); break;
+    }
+    k_fs_plane<<<dim3((unsigned)((max_pts + 255) / 256), (unsigned)ndom, (unsigned)slices), 256, 0, L.stream>>>(
+        q, fd, partial, tot_pts, slices);
+    k_fs_sum<<<(unsigned)((tot_pts + 255) / 256), 256, 0, L.stream>>>(partial, pl, tot_pts, slices);
+    switch (L.bs) {
+    case 16: k_fs_fold<16><<<nleafblk, 256, 0, L.stream>>>(f, L.tb, fd, c, pl, bv); break;
+    case 8: k_fs_fold<8><<<nleafblk, 256, 0, L.stream>>>(f, L.tb, fd, c, pl, bv); break;
+    default: k_fs_fold<4><<<nleafblk, 256, 0, L.stream>>>(f, L.tb, fd, c, pl, bv); break;
+    }
 }
 
 void launch_reduce_norms(const Launch &L) {

@@ -84,6 +84,8 @@ _SIGS = {
     "mg_face_gradient": ([_vp, _vp, _vp, _vp, ctypes.c_int], ctypes.c_int),
     "mg_divb_rhs": ([_vp, _vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "mg_divb_project": ([_vp, _vp, _vp, ctypes.c_int], ctypes.c_int),
+    "mg_freespace_bc": ([_vp, ctypes.c_int, _vp, ctypes.c_int], ctypes.c_int),
+    "mg_freespace_values": ([_vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "mg_profile_enable": ([_vp, ctypes.c_int], ctypes.c_int),
     "mg_profile_read": ([_vp, _P(_i64), _P(_d), _P(_d)], ctypes.c_int),
     "mg_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -95,6 +97,11 @@ for _name, (_args, _res) in _SIGS.items():
     _f.argtypes = _args
     _f.restype = _res
     globals()[_name] = _f
+
+
+def torch_float64():
+    import torch
+    return torch.float64
 
 
 class MGError(RuntimeError):
@@ -332,6 +339,28 @@ class Tree:
             raise ValueError("B and e must both be on the device or both on the host")
         _check(mg_divb_project(self.h, pb, pe, db), self.h)
         return b, ee
+
+    # ------------------------------------------------ free-space boundaries
+    def freespace_values(self):
+        n = _i64()
+        _check(mg_freespace_values(self.h, ctypes.byref(n)), self.h)
+        return int(n.value)
+
+    def freespace_bc(self, coarsen=1, values=False, out=None):
+        """Folds the free-space Dirichlet values of the current right-hand side into it
+        (potential of the right-hand side restricted by 2^coarsen).  With values=True
+        returns them (numpy, face-by-face order); with out (a CUDA float64 tensor of
+        freespace_values() elements) writes them there on the device."""
+        if out is not None:
+            assert out.is_cuda and out.dtype == torch_float64() and out.numel() == self.freespace_values()
+            _check(mg_freespace_bc(self.h, int(coarsen), _vp(out.data_ptr()), 1), self.h)
+            return out
+        if values:
+            a = np.zeros(self.freespace_values())
+            _check(mg_freespace_bc(self.h, int(coarsen), a.ctypes.data_as(_vp), 0), self.h)
+            return a
+        _check(mg_freespace_bc(self.h, int(coarsen), None, 0), self.h)
+        return None
 
     # ------------------------------------------------------------- profiling
     def profile_enable(self, on=True):

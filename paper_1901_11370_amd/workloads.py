@@ -339,5 +339,15 @@ def freespace_gauss(sizes: Sequence[int] = (64,), sigma: float = 0.1, bs: int = 
     def rhs(i, lay):
         x = cell_centres(lay, doms[i]) - np.asarray(r0s[i])
         return -np.exp(-np.sum(x * x, axis=1) / sigma ** 2) / (sigma ** 3 * np.pi ** 1.5)
+
+    def target(i, lay):
+        # the closed-form free-space solution erf(r / sigma) / (4 pi r)
+        from scipy.special import erf
+        x = cell_centres(lay, doms[i]) - np.asarray(r0s[i])
+        r = np.sqrt(np.sum(x * x, axis=1))
+        out = np.full(r.shape, 1.0 / (2.0 * np.pi ** 1.5 * sigma))
+        nz = r > 1e-12
+        out[nz] = erf(r[nz] / sigma) / (4.0 * np.pi * r[nz])
+        return out
     name = "freespace_gauss_" + "_".join(str(n) for n in sizes)
-    return Workload(name, doms, bs=bs, rhs=rhs, note=f"sigma={sigma}; centres {r0s}")
+    return Workload(name, doms, bs=bs, rhs=rhs, target=target, note=f"sigma={sigma}; centres {r0s}")
