@@ -1324,7 +1324,7 @@ int mg_freespace_bc(mg_tree *t, int coarsen, double *bvals, int on_device) {
     const int64_t room = n - ptot - bstage;
     if (qtot + fd_words > n || room < ptot) return fail(t, MG_ERR_ARG, "grids too small for the free-space scratch");
     const int wgs = (int)((max_pts + 255) / 256) * T.ndom;
-    int slices = std::max(1, (1024 + wgs - 1) / wgs);
+    int slices = std::max(1, (4096 + wgs - 1) / wgs);   // about 4096 workgroups in all
     slices = (int)std::min<int64_t>(std::min(slices, 64), room / ptot);
     double *q = t->d_stage;
     FsDom *dfd = reinterpret_cast<FsDom *>(t->d_stage + qtot);
