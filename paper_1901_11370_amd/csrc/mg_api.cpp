@@ -392,8 +392,12 @@ struct Driver {
             K<T>::fas(L, P, l - 1, t->d_parents[l - 1], (int)t->T.parents_of_level[l - 1].size(), m, v);
     }
     // The correction pushes same-level and boundary ghosts; coarse-fine ghosts follow.
-    void correct(int l, uint64_t m) {
-        K<T>::correct(L, P, l, lvb0(t, l), lvnb(t, l), m);
+    // next_steps: smoothing steps that follow on level l; with red-black Gauss-Seidel
+    // and no coarse-fine faces the first half-sweep rewrites colour 0 without reading it,
+    // so only colour 1 needs the correction (blocks on physical faces excepted).
+    void correct(int l, uint64_t m, int next_steps) {
+        const bool half = next_steps > 0 && !jacobi(t) && !t->T.refined;
+        K<T>::correct(L, P, l, lvb0(t, l), lvnb(t, l), m, half);
         cf_refresh(l, m);
     }
     // ---- tail levels: the large ones (per domain) as multi-workgroup launches, the
@@ -467,7 +471,7 @@ struct Driver {
         enter_tail(m);
         tail_vcycle(nt - 1, m);
         for (int l = nt; l <= top; l++) {
-            correct(l, m);
+            correct(l, m, t->prm.n_up);
             smooth(l, m, t->prm.n_up);
         }
     }
@@ -494,7 +498,7 @@ struct Driver {
         }
         for (int l = nt; l <= top; l++) {
             uint64_t m = mask_top_at_least(t, l);
-            correct(l, m);
+            correct(l, m, t->prm.n_down);   // the V-cycle starts by smoothing level l
             vcycle(l, m);
         }
     }

@@ -101,8 +101,10 @@ struct K {
                               uint64_t mask, int mode, bool var);
     static void fas(const Launch &L, const Plane<T> &P, int lev, const int32_t *list, int nlist,
                     uint64_t mask, bool var);
+    // half: only colour 1 (and blocks with a physical face whole): a colour-0 half-sweep
+    // follows on a level without coarse-fine faces
     static void correct(const Launch &L, const Plane<T> &P, int lev, int b0, int nb,
-                        uint64_t mask);
+                        uint64_t mask, bool half = false);
     static void tail(const Launch &L, const Plane<T> &P, int mode, uint64_t mask,
                      const TailParams &tp, bool var);
     static void tail_eps(const Launch &L, const Plane<T> &P);

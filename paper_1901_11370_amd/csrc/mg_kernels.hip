@@ -799,7 +799,12 @@ __global__ void __launch_bounds__(256) k_fas(Plane<T> P, DevTables tb, int lev, 
 // halo is staged in LDS; the fine block is updated with unit stride and its boundary
 // values pushed into the mirroring ghosts.
 // (SPLIT workgroups per block on levels with few blocks, as for the smoothing.)
-template <typename T, int D, int BS, int SPLIT>
+// HALF: a red-black half-sweep of colour 0 follows on a level without coarse-fine
+// faces.  It reads only colour 1 and the colour-1 ghost halves and rewrites every
+// colour-0 cell and ghost, so only colour 1 is corrected -- except in blocks with a
+// physical face, whose colour-0 boundary cells are read through the ghosts that mirror
+// them (Dirichlet, Neumann): those blocks correct both colours.
+template <typename T, int D, int BS, int SPLIT, bool HALF>
 __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int lev, int b0, uint64_t mask,
                                                  int nt) {
     using g = G<D, BS>;
@@ -807,10 +812,13 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
     constexpr int NBOX = D == 3 ? HP * HP * HP : HP * HP;
     constexpr int TPB = g::NC < 256 ? g::NC : 256;
     static_assert(SPLIT == 1 || g::NC % (TPB * SPLIT) == 0, "SPLIT must divide the block");
+    // cells of one pass: the whole block, or (HALF) one colour, split over SPLIT parts
+    constexpr int NPASS = (HALF ? g::NH : g::NC) / SPLIT;
     __shared__ T s_d[NBOX];
     const int nbl = gridDim.x / SPLIT;   // parts of a block nb workgroups apart (same XCD)
     const int64_t b = b0 + (SPLIT == 1 ? (int)blockIdx.x : (int)blockIdx.x % nbl);
-    const int t0 = SPLIT == 1 ? 0 : (blockIdx.x / nbl) * (g::NC / SPLIT);
+    const int part = SPLIT == 1 ? 0 : (int)blockIdx.x / nbl;
+    const int t0 = (HALF ? g::NH : 0) + part * NPASS;   // first storage index of this part
     const int tid = threadIdx.x;
     // the block's tables, all independent loads; the octant of the block in its parent
     // follows from its own origin (block coordinates' parity)
@@ -822,14 +830,14 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
     int po[3] = {0, 0, 0};
     for (int a = 0; a < D; a++) po[a] = ((gc0[a] / HB) & 1) * HB;
     constexpr int ITB = (NBOX + TPB - 1) / TPB;
-    constexpr int IT = (g::NC / SPLIT + TPB - 1) / TPB;
+    constexpr int IT = (NPASS + TPB - 1) / TPB;
     const TailGeo tg = tail_geo(tb, dm, nt - 1, D);
     // issue all loads first: the fine values this thread updates, then the staged box
     T vr[IT];
 #pragma unroll
     for (int m = 0; m < IT; m++) {
-        const int t = t0 + tid + m * TPB;
-        vr[m] = P.v[b * g::NC + (g::NC % TPB == 0 || t < g::NC ? t : 0)];
+        const int u = tid + m * TPB;
+        vr[m] = P.v[b * g::NC + t0 + (NPASS % TPB == 0 || u < NPASS ? u : 0)];
     }
     // box cell -> addresses of v and v_old (edges and corners of the halo, never
     // used, read the box centre instead)
@@ -865,10 +873,7 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
     }
     __syncthreads();
     if (!((mask >> dm) & 1)) return;
-#pragma unroll
-    for (int m = 0; m < IT; m++) {
-        const int t = t0 + tid + m * TPB;
-        if (g::NC % TPB != 0 && t >= g::NC) break;
+    auto update = [&](int t, T vold) {
         int i, j, k;
         g::decode(t, i, j, k);
         const int x = (i >> 1) + 1, y = (j >> 1) + 1, z = D == 3 ? (k >> 1) + 1 : 0;
@@ -878,9 +883,29 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
         T corr;
         if (D == 2) corr = T(0.25) * (T(2) * d0 + dx + dy);
         else corr = T(0.25) * (d0 + dx + dy + s_d[c0 + sz * HP * HP]);
-        const T nv = vr[m] + corr;
+        const T nv = vold + corr;
         P.v[b * g::NC + t] = nv;
         push_ghosts<T, D, BS>(P.vg, cx, b, i, j, k, nv);
+    };
+#pragma unroll
+    for (int m = 0; m < IT; m++) {
+        const int u = tid + m * TPB;
+        if (NPASS % TPB != 0 && u >= NPASS) break;
+        update(t0 + u, vr[m]);
+    }
+    if (HALF) {
+        bool phys = false;
+#pragma unroll
+        for (int f = 0; f < 2 * D; f++) phys = phys || cx.nbr[f] == -1;
+        if (phys) {
+#pragma unroll
+            for (int m = 0; m < IT; m++) {
+                const int u = tid + m * TPB;
+                if (NPASS % TPB != 0 && u >= NPASS) break;
+                const int t = part * NPASS + u;   // colour 0
+                update(t, P.v[b * g::NC + t]);
+            }
+        }
     }
 }
 
@@ -2466,14 +2491,19 @@ void K<T>::fas(const Launch &L, const Plane<T> &P, int lev, const int32_t *list,
 }
 
 template <typename T>
-void K<T>::correct(const Launch &L, const Plane<T> &P, int lev, int b0, int nb, uint64_t mask) {
+void K<T>::correct(const Launch &L, const Plane<T> &P, int lev, int b0, int nb, uint64_t mask, bool half) {
     if (nb <= 0) return;
     DISPATCH_DB(L, {
         constexpr int NC = G<D, BS>::NC;
         constexpr int TPB = NC < 256 ? NC : 256;
         constexpr int SP = NC / TPB >= 4 ? 4 : 1;
-        if (SP > 1 && nb <= 256) k_correct<T, D, BS, SP><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, L.nt);
-        else k_correct<T, D, BS, 1><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, L.nt);
+        if (half) {
+            if (SP > 1 && nb <= 256) k_correct<T, D, BS, SP, true><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, L.nt);
+            else k_correct<T, D, BS, 1, true><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, L.nt);
+        } else {
+            if (SP > 1 && nb <= 256) k_correct<T, D, BS, SP, false><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, L.nt);
+            else k_correct<T, D, BS, 1, false><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, mask, L.nt);
+        }
     });
 }
 
