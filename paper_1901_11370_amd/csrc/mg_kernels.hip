@@ -317,11 +317,13 @@ __device__ __forceinline__ void push_ghosts(T *__restrict__ vg, const BlockCtx<D
 // ZERO: the other colour and its ghosts are known to be zero (the first half-sweep of a
 // correction solve from e = 0, homogeneous boundary values), so they are not read, and
 // this colour's ghosts on physical faces are set to zero for the next half-sweep.
-template <typename T, int D, int BS, bool VAR, int SPLIT, bool ZERO>
-__global__ void __launch_bounds__(256) k_gsrb(Plane<T> P, DevTables tb, int lev, int b0, int colour,
-                                              uint64_t mask) {
+// WIDE = 2 (levels of a few hundred blocks): 512-thread workgroups, twice the waves per
+// CU for the same block count.
+template <typename T, int D, int BS, bool VAR, int SPLIT, bool ZERO, int WIDE = 1>
+__global__ void __launch_bounds__(256 * WIDE) k_gsrb(Plane<T> P, DevTables tb, int lev, int b0, int colour,
+                                                     uint64_t mask) {
     using g = G<D, BS>;
-    constexpr int TPB = g::NH < 256 ? g::NH : 256;
+    constexpr int TPB = (g::NH < 256 ? g::NH : 256) * WIDE;
     constexpr int HF = g::NF / 2;               // ghosts of one colour per face
     constexpr int NGH = 2 * D * HF;
     constexpr int IT = g::NH / TPB / SPLIT;
@@ -2418,6 +2420,7 @@ void K<T>::gsrb(const Launch &L, const Plane<T> &P, int lev, int b0, int nb, int
         constexpr int NH = G<D, BS>::NH;
         constexpr int TPB = NH < 256 ? NH : 256;
         constexpr int SP = NH / TPB >= 4 ? 4 : 1;
+        constexpr int WF = SP > 1 ? 2 : 1;   // large levels: 512-thread workgroups
         if (zero) {
             // only the FP32 correction solves start from zero
             if constexpr (sizeof(T) == 4) {
@@ -2431,17 +2434,21 @@ void K<T>::gsrb(const Launch &L, const Plane<T> &P, int lev, int b0, int nb, int
             }
         } else if (ev0) {
             if (var)
-                hipExtLaunchKernelGGL((k_gsrb<T, D, BS, true, 1, false>), dim3(nb), dim3(TPB), 0, L.stream, ev0, ev1, 0,
+                hipExtLaunchKernelGGL((k_gsrb<T, D, BS, true, 1, false, WF>), dim3(nb), dim3(TPB * WF), 0, L.stream, ev0, ev1, 0,
                                       P, L.tb, lev, b0, colour, mask);
             else
-                hipExtLaunchKernelGGL((k_gsrb<T, D, BS, false, 1, false>), dim3(nb), dim3(TPB), 0, L.stream, ev0, ev1,
+                hipExtLaunchKernelGGL((k_gsrb<T, D, BS, false, 1, false, WF>), dim3(nb), dim3(TPB * WF), 0, L.stream, ev0, ev1,
                                       0, P, L.tb, lev, b0, colour, mask);
         } else if (SP > 1 && nb <= 256) {
             if (var) k_gsrb<T, D, BS, true, SP, false><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
             else k_gsrb<T, D, BS, false, SP, false><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+        } else if (SP > 1 && nb <= 1024) {
+            constexpr int WD = SP > 1 ? 2 : 1;
+            if (var) k_gsrb<T, D, BS, true, 1, false, WD><<<nb, TPB * WD, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+            else k_gsrb<T, D, BS, false, 1, false, WD><<<nb, TPB * WD, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
         } else {
-            if (var) k_gsrb<T, D, BS, true, 1, false><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
-            else k_gsrb<T, D, BS, false, 1, false><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+            if (var) k_gsrb<T, D, BS, true, 1, false, WF><<<nb, TPB * WF, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+            else k_gsrb<T, D, BS, false, 1, false, WF><<<nb, TPB * WF, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
         }
     });
 }
