@@ -362,8 +362,7 @@ __global__ void __launch_bounds__(256 * WIDE) k_gsrb(Plane<T> P, DevTables tb, i
         st_o.store(s_o);
         st_g.store(s_g);
     } else {
-        for (int q = tid; q < g::NH; q += TPB) s_o[q] = T(0);
-        for (int q = tid; q < NGH; q += TPB) s_g[q] = T(0);
+        // (the other colour is zero: it is neither staged nor read below)
         // On a physical face the ghosts of this colour mirror cells of the other colour
         // (zero), so with the homogeneous boundary values of a correction solve they are
         // zero as well; the next half-sweep reads them.
@@ -380,7 +379,7 @@ __global__ void __launch_bounds__(256 * WIDE) k_gsrb(Plane<T> P, DevTables tb, i
         st_eo.store(s_eo);
         st_eg.store(s_eg);
     }
-    __syncthreads();
+    if (!ZERO || VAR) __syncthreads();   // nothing is staged in the zero form without eps
     if (!((mask >> cx.dm) & 1)) return;
     T ih2[3];
 #pragma unroll
@@ -406,15 +405,16 @@ __global__ void __launch_bounds__(256 * WIDE) k_gsrb(Plane<T> P, DevTables tb, i
         const T fval = fr[m];
         double fm, fp;
         axi_factors<D>(tb, cx.dm, cx.h[0], cx.orgx + i, fm, fp);
+        // the other colour's value across face f (zero in the zero form)
+        auto nbv = [&](int f) -> T { return ZERO ? T(0) : (gho[f] ? s_g[off[f]] : s_o[off[f]]); };
         if (!VAR) {
             if (D == 2 && tb.axi) {
-                num += ih2[0] * (T(fm) * (gho[0] ? s_g[off[0]] : s_o[off[0]]) +
-                                 T(fp) * (gho[1] ? s_g[off[1]] : s_o[off[1]]));
+                num += ih2[0] * (T(fm) * nbv(0) + T(fp) * nbv(1));
 #pragma unroll
-                for (int f = 2; f < 2 * D; f++) num += ih2[f >> 1] * (gho[f] ? s_g[off[f]] : s_o[off[f]]);
+                for (int f = 2; f < 2 * D; f++) num += ih2[f >> 1] * nbv(f);
             } else {
 #pragma unroll
-                for (int f = 0; f < 2 * D; f++) num += ih2[f >> 1] * (gho[f] ? s_g[off[f]] : s_o[off[f]]);
+                for (int f = 0; f < 2 * D; f++) num += ih2[f >> 1] * nbv(f);
             }
 #pragma unroll
             for (int a = 0; a < D; a++) den += T(2) * ih2[a];
@@ -426,7 +426,7 @@ __global__ void __launch_bounds__(256 * WIDE) k_gsrb(Plane<T> P, DevTables tb, i
                 T w = harm(e0, en) * ih2[f >> 1];
                 if (f == 0) w *= T(fm);
                 if (f == 1) w *= T(fp);
-                num += w * (gho[f] ? s_g[off[f]] : s_o[off[f]]);
+                num += w * nbv(f);
                 den += w;
             }
         }
@@ -2428,8 +2428,8 @@ void K<T>::gsrb(const Launch &L, const Plane<T> &P, int lev, int b0, int nb, int
                     if (var) k_gsrb<T, D, BS, true, SP, true><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
                     else k_gsrb<T, D, BS, false, SP, true><<<nb * SP, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
                 } else {
-                    if (var) k_gsrb<T, D, BS, true, 1, true><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
-                    else k_gsrb<T, D, BS, false, 1, true><<<nb, TPB, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+                    if (var) k_gsrb<T, D, BS, true, 1, true, WF><<<nb, TPB * WF, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
+                    else k_gsrb<T, D, BS, false, 1, true, WF><<<nb, TPB * WF, 0, L.stream>>>(P, L.tb, lev, b0, colour, mask);
                 }
             }
         } else if (ev0) {
