@@ -145,6 +145,38 @@ def test_large_tail_grids_3d_periodic_neumann():
     _run(w, "vfvv")
 
 
+def _wide_level_workload():
+    # 128 x 128 x 96 cells in 16^3 blocks: 384 blocks on the finest level, which the
+    # sweep runs with 512-thread workgroups; variable eps and all three boundary kinds
+    dom = W.Domain(3, [128, 128, 96], [0, 0, 0], [1.0, 1.0, 0.75],
+                   [W.DIRICHLET, W.NEUMANN, W.PERIODIC, W.PERIODIC, W.DIRICHLET, W.DIRICHLET],
+                   [0.5, -0.2, 0.0, 0.0, 0.0, 1.0])
+    g = W.Gaussians(np.array([[0.4, 0.6, 0.3]]), np.array([8.0]), np.array([0.1]))
+    return W.Workload("widelevel3d", [dom], bs=16, variable_eps=True,
+                      rhs=lambda i, lay: g(W.cell_centres(lay, dom)), eps=lambda i, lay: _smooth_eps(dom, lay))
+
+
+def test_wide_sweep_level_variable_eps():
+    _run(_wide_level_workload(), "fvv")
+
+
+def test_wide_sweep_level_variable_eps_mixed():
+    # the FP32 forms of the same level (zero-start and ordinary 512-thread sweeps)
+    w = _wide_level_workload()
+    t = gpu_tree(w, precision=1)
+    o = oracle_trees(w)[0]
+    f, e = inputs(w, t)
+    t.set_eps(np.concatenate(e))
+    t.set_rhs(np.concatenate(f))
+    cycles, rc = t.solve(rel_tol=1e-10, max_cycles=40)
+    o.set_eps(e[0])
+    o.set_rhs(f[0])
+    o.solve(rel_tol=1e-11, max_cycles=40)
+    err = rel_err(t.get_phi(), o.get_phi())
+    print("wide level mixed", cycles, err, flush=True)
+    assert rc == 0 and err <= 1e-8
+
+
 def test_face_gradient_matches_reference():
     w = W.config5(sizes=(32, 48))
     t = gpu_tree(w)
