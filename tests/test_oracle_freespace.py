@@ -85,20 +85,43 @@ def test_interpolation_is_exact_on_linear_planes():
 
 
 def test_fold_equals_the_solver_dirichlet_faces():
-    # constant value a on every face: folding a into f and solving with homogeneous
-    # faces gives the solution of the solver's own Dirichlet a faces
-    a, n = 0.3, 32
+    # a different constant value on every face: folding them into f and solving with
+    # homogeneous faces gives the solution of the solver's own Dirichlet faces
+    vals, n = [0.3, -0.2, 0.5, 0.1, -0.4, 0.25], 32
     rng = np.random.default_rng(5)
-    t_ref = _tree(n, bc_value=a)
+    t_ref = OracleTree(3, (n, n, n), (-0.5,) * 3, (0.5,) * 3, [DIRICHLET] * 6, bc_value=vals, bs=16)
     f = rng.standard_normal(t_ref.n_leaf)
     t_ref.set_rhs(f)
     t_ref.solve(rel_tol=1e-13, max_cycles=40)
     ref = t_ref.get_phi()
     t0 = _tree(n)
-    bv = [np.full((n, n), a)] * 6
+    bv = [np.full((n, n), a) for a in vals]
     t0.set_rhs(FS.fold(t0, f, bv))
     t0.solve(rel_tol=1e-13, max_cycles=40)
     assert np.max(np.abs(t0.get_phi() - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
+def test_boundary_values_at_the_leaf_faces():
+    # the values of every face at its leaf face centres, placed here from the grid alone,
+    # against eq. gauss-sol for an off-centre source (a face computed on the opposite
+    # side or a transposed face fails)
+    r0 = (0.12, -0.07, 0.05)
+    n = 32
+    w = W.freespace_gauss((n,), offsets=[r0])
+    t = _tree(n)
+    f = _rhs(t, w)
+    c = -0.5 + (np.arange(n) + 0.5) / n
+    C2, C1 = np.meshgrid(c, c, indexing="ij")   # [j2, j1]: lower in-plane axis fastest
+    for k, tol in ((0, 1e-6), (1, 1e-2)):   # k = 1: linear interpolation between 1/16 planes
+        bv = FS.boundary_values(t, f, k)
+        for face in range(6):
+            a = face // 2
+            t1, t2 = [b for b in range(3) if b != a]
+            P = [None] * 3
+            P[a] = np.full_like(C1, 0.5 if face & 1 else -0.5)
+            P[t1], P[t2] = C1, C2
+            exact = FS.gauss_sol(P[0], P[1], P[2], r0=r0)
+            assert np.max(np.abs(bv[face] - exact)) < tol * np.max(np.abs(exact)), (k, face)
 
 
 def _error(n, k):
