@@ -40,7 +40,8 @@ def _args():
     p.add_argument("--cpu-sample-cycles", type=int, default=1, help="V-cycles after the FMG in the CPU sample")
     p.add_argument("--workload", default="periodic256",
                    choices=["periodic256", "dirichlet2d", "amr-literal", "amr-nested", "varcoef-nested", "batch",
-                            "tree-build", "paper-scaling", "convergence", "helmholtz", "divb-clean", "freespace"],
+                            "tree-build", "paper-scaling", "convergence", "helmholtz", "divb-clean", "freespace",
+                            "freespace-convergence"],
                    help="periodic256 is the benchmark line; the others print report lines")
     p.add_argument("--max-cycles", type=int, default=60)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -408,6 +409,48 @@ def report(a):
         out["ms_per_step"] = out["fp64_coarsen2"]["ms_total"]
         out["note"] = ("ms_boundary_values includes setting f (a device copy); pair terms: plane points x "
                        "coarse cells of the direct Green's-function sum")
+        print(json.dumps(out), flush=True)
+        return
+    if a.workload == "freespace-convergence":
+        # the paper's Fig. free-space-error (Sec. 3.2): error of the solution after two FMG
+        # cycles against eq. gauss-sol versus grid size, with the free-space values taken
+        # one and two levels below the finest (charges 2x and 4x coarser)
+        out = dict(base, metric="free-space test: error after two FMG cycles and at the tolerance", unit="L2 error",
+                   higher_is_better=False, dtype="f64",
+                   config={"workload": "freespace_gauss_sigma0.1_fmg2_64-512"})
+        rows = []
+        for n in (64, 128, 256, 512):
+            w = W.freespace_gauss((n,))
+            lay = None
+            for k in (1, 2):
+                t = _tree_of(w, mg.MG_FP64, mg)
+                if lay is None:
+                    lay = t.leaf_layout()
+                    f = torch.from_numpy(w.rhs(0, lay[:, 1:])).cuda()
+                    exact = w.target(0, lay[:, 1:])
+                t.set_rhs(f)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                t.freespace_bc(k)
+                torch.cuda.synchronize()
+                ms_bc = (time.perf_counter() - t0) * 1e3
+                t.set_phi(torch.zeros_like(f))
+                t.fmg(2)
+                e = t.get_phi() - exact
+                ex = np.abs(exact).max()
+                row = {"n": n, "levels_below": k, "fmg2_err_l2": float(np.sqrt(np.mean(e * e))),
+                       "fmg2_err_max_rel": float(np.max(np.abs(e)) / ex), "ms_boundary_values": ms_bc}
+                # then V-cycles to the tolerance: the discretisation error itself
+                c, rc = t.solve(rel_tol=a.tol, max_cycles=MAX_CYCLES, fmg_first=False, raise_on_fail=False)
+                e = t.get_phi() - exact
+                row.update({"cycles_after": c, "err_l2": float(np.sqrt(np.mean(e * e))),
+                            "err_max_rel": float(np.max(np.abs(e)) / ex)})
+                rows.append(row)
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+                del t, e
+        out["rows"] = rows
+        out["value"] = rows[-1]["err_l2"]
+        out["ms_per_step"] = None
         print(json.dumps(out), flush=True)
         return
     if a.workload == "tree-build":
