@@ -164,6 +164,25 @@ def freespace_rhs(tree, f, k):
     return fold(tree, f, bv), bv
 
 
+def far_field_guess(tree, f, k):
+    """Initial guess for the cycles (reading R22): the potential -Q / (4 pi r) of the
+    coarse charges' total Q placed at their centroid, r at least one coarse spacing, on
+    the leaf cells (leaf order); zero for a neutral source (|Q| <= 1e-12 sum |q|).  The
+    paper starts from its uniform-grid free-space solution instead."""
+    q, hc = coarse_charges(tree, f, k)
+    qq = q.ravel()
+    cen = _centres(tree, hc, [q.shape[2], q.shape[1], q.shape[0]])
+    lay = tree.leaf_layout()
+    Q = qq.sum()
+    if not abs(Q) > 1e-12 * np.abs(qq).sum():
+        return np.zeros(len(lay))
+    xbar = (qq[:, None] * cen).sum(axis=0) / Q
+    h = (tree.hi - tree.lo) / tree.base
+    x = np.stack([tree.lo[a] + (lay[:, 1 + a] + 0.5) * h[a] for a in range(3)], axis=1)
+    r = np.maximum(np.sqrt(((x - xbar) ** 2).sum(axis=1)), hc.min())
+    return -Q / (FOUR_PI * r)
+
+
 # ------------------------------------------------------------ Sec. 3.2 test problem
 def gauss_rhs(x, y, z, sigma=0.1, r0=(0.0, 0.0, 0.0)):
     """eq. gauss-rhs: -exp(-|r - r0|^2 / sigma^2) / (sigma^3 pi^(3/2))."""

@@ -156,3 +156,26 @@ def test_checks():
     t = _tree(48)
     with pytest.raises(ValueError):
         FS.coarse_charges(t, np.zeros(t.n_leaf), 5)
+
+
+def test_far_field_guess_matches_the_far_solution():
+    # outside the source the Gaussian's potential is that of its total charge at its
+    # centre (eq. gauss-sol with erf -> 1), so the guess matches it there, for a centred
+    # and an off-centre source (the centroid); a neutral source gives zero
+    for r0 in ((0.0, 0.0, 0.0), (0.12, -0.07, 0.05)):
+        w = W.freespace_gauss((32,), offsets=[r0])
+        t = _tree(32)
+        lay = t.leaf_layout()
+        g = FS.far_field_guess(t, w.rhs(0, lay), 1)
+        x = W.cell_centres(lay, w.domains[0])
+        r = np.sqrt(((x - np.asarray(r0)) ** 2).sum(axis=1))
+        far = r > 0.35
+        exact = FS.gauss_sol(x[:, 0], x[:, 1], x[:, 2], r0=r0)
+        assert np.max(np.abs(g[far] - exact[far])) < 1e-5 * np.max(np.abs(exact[far]))
+        assert np.all(np.isfinite(g))
+    t = _tree(32)
+    lay = t.leaf_layout()
+    x = W.cell_centres(lay, W.freespace_gauss((32,)).domains[0])
+    pos = np.exp(-((x - 0.1) ** 2).sum(axis=1) / 0.01)
+    neg = np.exp(-((x + 0.1) ** 2).sum(axis=1) / 0.01)
+    assert np.all(FS.far_field_guess(t, pos - neg, 1) == 0.0)
