@@ -246,6 +246,17 @@ int mg_divb_project(mg_tree *t, double *leaf_B, double *leaf_e, int on_device);
 int mg_freespace_bc(mg_tree *t, int coarsen, double *bvals, int on_device);
 int mg_freespace_values(const mg_tree *t, int64_t *n_values);
 
+/* Initial guess for a free-space solve (same requirements and coarsen as
+ * mg_freespace_bc; call it before mg_freespace_bc, while f is the plain right-hand
+ * side): sets phi on the leaves to the far-field potential -Q / (4 pi r) of the
+ * coarse charges' total Q placed at their centroid, r at least one coarse spacing, or
+ * to zero for a neutral source.  The paper starts the cycles from the uniform-grid
+ * free-space solution; this cheaper guess serves the same purpose: near the boundary
+ * it already matches the folded values, so FMG's coarse problems are consistent there
+ * (from phi = 0 they see a boundary forcing that doubles per level).  Uses the staging
+ * buffers and synchronises the stream. */
+int mg_freespace_guess(mg_tree *t, int coarsen);
+
 /* Kernel timing: when enabled, HIP events bracket every launch of the smoothing
  * kernel on the finest level (on the bound stream); mg_profile_read returns the
  * number of such launches and their total milliseconds since enabling. */

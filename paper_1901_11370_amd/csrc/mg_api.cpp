@@ -1271,7 +1271,10 @@ int mg_divb_project(mg_tree *t, double *leaf_B, double *leaf_e, int on_device) {
     return MG_OK;
 }
 
-int mg_freespace_bc(mg_tree *t, int coarsen, double *bvals, int on_device) {
+// Checks and per-domain geometry of the free-space boundaries (mg_freespace_bc,
+// mg_freespace_guess).
+static int fs_setup(mg_tree *t, int coarsen, std::vector<FsDom> &fd, int64_t &qtot, int64_t &ptot, int64_t &btot,
+                    int &max_pts) {
     int rc = require_bound(t);
     if (rc) return rc;
     const HostTree &T = t->T;
@@ -1282,9 +1285,9 @@ int mg_freespace_bc(mg_tree *t, int coarsen, double *bvals, int on_device) {
     if (coarsen < 1 || (1 << coarsen) > T.bs)
         return fail(t, MG_ERR_ARG, "coarsen must satisfy 1 <= coarsen and 2^coarsen <= block size");
     const int c = 1 << coarsen;
-    std::vector<FsDom> fd(T.ndom);
-    int64_t qtot = 0, ptot = 0, btot = 0;
-    int max_pts = 0;
+    fd.assign(T.ndom, FsDom{});
+    qtot = ptot = btot = 0;
+    max_pts = 0;
     for (int i = 0; i < T.ndom; i++) {
         const mg_domain &d = T.doms[i].d;
         for (int f = 0; f < 6; f++)
@@ -1318,6 +1321,17 @@ int mg_freespace_bc(mg_tree *t, int coarsen, double *bvals, int on_device) {
         ptot += pp;
         btot += bb;
     }
+    return MG_OK;
+}
+
+int mg_freespace_bc(mg_tree *t, int coarsen, double *bvals, int on_device) {
+    std::vector<FsDom> fd;
+    int64_t qtot, ptot, btot;
+    int max_pts;
+    int rc = fs_setup(t, coarsen, fd, qtot, ptot, btot, max_pts);
+    if (rc) return rc;
+    const HostTree &T = t->T;
+    const int c = 1 << coarsen;
     // scratch in the two leaf-sized staging buffers: charges and the domain table in the
     // first; planes, staged boundary values and the slices' partial sums in the second
     const int64_t n = T.nleaf_cells;
@@ -1340,6 +1354,28 @@ int mg_freespace_bc(mg_tree *t, int coarsen, double *bvals, int on_device) {
     if ((rc = check_launch(t))) return rc;
     if (bvals && !on_device)
         HIP_OR_FAIL(t, hipMemcpyAsync(bvals, bst, (size_t)btot * 8, hipMemcpyDeviceToHost, t->stream));
+    HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));   // the domain table lives on this stack
+    return MG_OK;
+}
+
+int mg_freespace_guess(mg_tree *t, int coarsen) {
+    std::vector<FsDom> fd;
+    int64_t qtot, ptot, btot;
+    int max_pts;
+    int rc = fs_setup(t, coarsen, fd, qtot, ptot, btot, max_pts);
+    if (rc) return rc;
+    const HostTree &T = t->T;
+    const int64_t n = T.nleaf_cells;
+    const int64_t fd_words = ((int64_t)sizeof(FsDom) * T.ndom + 7) / 8;
+    if (qtot + fd_words + 5 * T.ndom > n) return fail(t, MG_ERR_ARG, "grids too small for the free-space scratch");
+    double *q = t->d_stage;
+    FsDom *dfd = reinterpret_cast<FsDom *>(t->d_stage + qtot);
+    double *mom = t->d_stage + qtot + fd_words;
+    HIP_OR_FAIL(t, hipMemcpyAsync(dfd, fd.data(), sizeof(FsDom) * T.ndom, hipMemcpyHostToDevice, t->stream));
+    launch_freespace_guess(launch(t, false), t->P64.f, dfd, T.ndom, 1 << coarsen, q, mom, t->d_stage2,
+                           (int)t->nleafblk, n);
+    if ((rc = check_launch(t))) return rc;
+    if ((rc = mg_set_phi(t, t->d_stage2, 1))) return rc;
     HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));   // the domain table lives on this stack
     return MG_OK;
 }

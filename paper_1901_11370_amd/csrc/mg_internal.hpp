@@ -178,6 +178,10 @@ struct FsDom {
 // the values.  partial holds S * total plane points.
 void launch_freespace(const Launch &L, double *f, const FsDom *fd, int ndom, int max_pts, int64_t tot_pts,
                       int c, int slices, double *q, double *partial, double *pl, double *bv, int nleafblk);
+// Far-field (monopole) potential of the coarse charges of f on the leaf cells, leaf
+// order; q and mom (5 values per domain) are scratch.
+void launch_freespace_guess(const Launch &L, const double *f, const FsDom *fd, int ndom, int c, double *q,
+                            double *mom, double *out, int nleafblk, int64_t nleaf_cells);
 void launch_face_gradient(const Launch &L, const Plane<double> &P, const double *lam_blocks,
                           const double *lam_g, double *out_leaf, int nleafblk);
 

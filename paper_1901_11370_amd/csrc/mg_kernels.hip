@@ -2317,6 +2317,66 @@ __global__ void __launch_bounds__(256) k_fs_fold(double *__restrict__ f, DevTabl
     }
 }
 
+// Far-field initial guess for a free-space solve: per domain the total charge Q, its
+// first moments and sum |q| of the coarse charges (one workgroup per domain, fixed
+// summation order), then on every leaf cell the potential -Q / (4 pi r) of Q at the
+// charge centroid, r at least one coarse spacing (zero for a neutral source).
+__global__ void __launch_bounds__(256) k_fs_moments(const double *__restrict__ q, const FsDom *__restrict__ fd,
+                                                    double *__restrict__ mom) {
+    __shared__ double red[5][256];
+    const FsDom *dp = fd + blockIdx.x;
+    const int nx = dp->nc[0], ny = dp->nc[1], nq = dp->nc[0] * dp->nc[1] * dp->nc[2];
+    double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int c = threadIdx.x; c < nq; c += 256) {
+        const double v = q[dp->qoff + c];
+        const int I = c % nx, J = (c / nx) % ny, K = c / (nx * ny);
+        a[0] += v;
+        a[1] += v * (dp->lo[0] + (I + 0.5) * dp->hc[0]);
+        a[2] += v * (dp->lo[1] + (J + 0.5) * dp->hc[1]);
+        a[3] += v * (dp->lo[2] + (K + 0.5) * dp->hc[2]);
+        a[4] += fabs(v);
+    }
+#pragma unroll
+    for (int m = 0; m < 5; m++) red[m][threadIdx.x] = a[m];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int m = 0; m < 5; m++) red[m][threadIdx.x] += red[m][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) mom[5 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+template <int BS>
+__global__ void __launch_bounds__(256) k_fs_guess(const FsDom *__restrict__ fd, const double *__restrict__ mom,
+                                                  DevTables tb, double *__restrict__ out, int64_t ncells) {
+    using g = G<3, BS>;
+    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (id >= ncells) return;
+    const int64_t r = id / g::NC;
+    const int t = (int)(id % g::NC);
+    const int64_t b = tb.leaf_blk[r];
+    const int dm = tb.dom[b];
+    const FsDom *dp = fd + dm;
+    const double *m = mom + 5 * dm;
+    const double Q = m[0];
+    if (!(fabs(Q) > 1e-12 * m[4])) {
+        out[id] = 0.0;
+        return;
+    }
+    const int ii[3] = {t % BS, (t / BS) % BS, t / (BS * BS)};
+    double d2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double x = dp->lo[a] + (tb.org[3 * b + a] + ii[a] + 0.5) * dp->h[a];
+        const double dx = x - m[1 + a] / Q;
+        d2 += dx * dx;
+    }
+    const double rmin = fmin(dp->hc[0], fmin(dp->hc[1], dp->hc[2]));
+    out[id] = -Q / (4.0 * M_PI * fmax(sqrt(d2), rmin));
+}
+
 // ================================================================ launchers
 #define HIPCHK(x) (x)
 
@@ -2749,6 +2809,23 @@ void launch_freespace(const Launch &L, double *f, const FsDom *fd, int ndom, int
     case 16: k_fs_fold<16><<<nleafblk, 256, 0, L.stream>>>(f, L.tb, fd, c, pl, bv); break;
     case 8: k_fs_fold<8><<<nleafblk, 256, 0, L.stream>>>(f, L.tb, fd, c, pl, bv); break;
     default: k_fs_fold<4><<<nleafblk, 256, 0, L.stream>>>(f, L.tb, fd, c, pl, bv); break;
+    }
+}
+
+void launch_freespace_guess(const Launch &L, const double *f, const FsDom *fd, int ndom, int c, double *q,
+                            double *mom, double *out, int nleafblk, int64_t nleaf_cells) {
+    if (nleaf_cells <= 0) return;
+    switch (L.bs) {
+    case 16: k_fs_charge<16><<<nleafblk, 256, 0, L.stream>>>(f, L.tb, fd, c, q); break;
+    case 8: k_fs_charge<8><<<nleafblk, 256, 0, L.stream>>>(f, L.tb, fd, c, q); break;
+    default: k_fs_charge<4><<<nleafblk, 256, 0, L.stream>>>(f, L.tb, fd, c, q); break;
+    }
+    k_fs_moments<<<ndom, 256, 0, L.stream>>>(q, fd, mom);
+    const unsigned grid = (unsigned)((nleaf_cells + 255) / 256);
+    switch (L.bs) {
+    case 16: k_fs_guess<16><<<grid, 256, 0, L.stream>>>(fd, mom, L.tb, out, nleaf_cells); break;
+    case 8: k_fs_guess<8><<<grid, 256, 0, L.stream>>>(fd, mom, L.tb, out, nleaf_cells); break;
+    default: k_fs_guess<4><<<grid, 256, 0, L.stream>>>(fd, mom, L.tb, out, nleaf_cells); break;
     }
 }
 

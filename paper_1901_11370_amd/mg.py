@@ -86,6 +86,7 @@ _SIGS = {
     "mg_divb_project": ([_vp, _vp, _vp, ctypes.c_int], ctypes.c_int),
     "mg_freespace_bc": ([_vp, ctypes.c_int, _vp, ctypes.c_int], ctypes.c_int),
     "mg_freespace_values": ([_vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "mg_freespace_guess": ([_vp, ctypes.c_int], ctypes.c_int),
     "mg_profile_enable": ([_vp, ctypes.c_int], ctypes.c_int),
     "mg_profile_read": ([_vp, _P(_i64), _P(_d), _P(_d)], ctypes.c_int),
     "mg_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -361,6 +362,10 @@ class Tree:
             return a
         _check(mg_freespace_bc(self.h, int(coarsen), None, 0), self.h)
         return None
+
+    def freespace_guess(self, coarsen=1):
+        """phi = far-field potential of the current right-hand side (before freespace_bc)."""
+        _check(mg_freespace_guess(self.h, int(coarsen)), self.h)
 
     # ------------------------------------------------------------- profiling
     def profile_enable(self, on=True):

@@ -161,3 +161,33 @@ def test_full_size_faces_match_reference():
         P[t1], P[t2] = C1, C2
         ex.append(FS.gauss_sol(P[0], P[1], P[2], r0=(0.03, -0.02, 0.01)).ravel())
     assert _rel(bv, np.concatenate(ex)) < 5e-4
+
+
+def test_far_field_guess_matches_reference():
+    w = W.freespace_gauss((32, 48), offsets=[(0.0, 0.0, 0.0), (0.1, -0.05, 0.07)])
+    t = gpu_tree(w)
+    fs = _inputs(w, t)
+    t.set_rhs(np.concatenate(fs))
+    t.freespace_guess(1)
+    for got, o, f in zip(split(t, t.get_phi()), oracle_trees(w), fs):
+        assert _rel(got, FS.far_field_guess(o, f, 1)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_fmg_from_the_far_field_guess(n):
+    # the paper's measure (error after two FMG cycles): from the guess FMG's coarse
+    # problems are consistent near the boundary, and two cycles reach the error of the
+    # solution converged to 1e-10
+    w = W.freespace_gauss((n,))
+    t = gpu_tree(w)
+    lay = t.leaf_layout()[:, 1:]
+    t.set_rhs(w.rhs(0, lay))
+    t.freespace_guess(1)
+    t.freespace_bc(1)
+    t.fmg(2)
+    exact = w.target(0, lay)
+    e2 = np.sqrt(np.mean((t.get_phi() - exact) ** 2))
+    t.solve(rel_tol=1e-10, max_cycles=30, fmg_first=False)
+    ec = np.sqrt(np.mean((t.get_phi() - exact) ** 2))
+    print(f"n={n}: L2 error after 2 FMG {e2:.3e}, converged {ec:.3e}", flush=True)
+    assert e2 < 1.3 * ec
