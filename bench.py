@@ -532,8 +532,8 @@ def main():
     global MAX_CYCLES
     MAX_CYCLES = a.max_cycles
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
-              "(see DESIGN.md for how the solver would shard)", file=sys.stderr)
+        print(f"bench.py: this benchmark runs on one GPU; --gpus {a.gpus} is not supported "
+              "(the solver has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
     if a.copy_calibration:
         copy_calibration(a.copy_calibration)

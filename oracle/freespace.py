@@ -11,7 +11,7 @@ the coupling the paper describes, in its order:
   3. the planes are interpolated linearly to the leaf faces, which gives the Dirichlet
      values;
   4. multigrid cycles solve the problem with these values.
-Readings (listed with the others of this build as R22):
+Readings where the paper leaves a choice:
   - step 2: the paper calls an external interpolating-scaling-function FFT solver; here
     the potential of the coarse cells, each a point charge q = f_c h_c^3 at its centre,
     is summed directly: phi(x) = -(1/4 pi) sum_c q_c / |x - x_c|;
@@ -165,7 +165,7 @@ def freespace_rhs(tree, f, k):
 
 
 def far_field_guess(tree, f, k):
-    """Initial guess for the cycles (reading R22): the potential -Q / (4 pi r) of the
+    """Initial guess for the cycles: the potential -Q / (4 pi r) of the
     coarse charges' total Q placed at their centroid, r at least one coarse spacing, on
     the leaf cells (leaf order); zero for a neutral source (|Q| <= 1e-12 sum |q|).  The
     paper starts from its uniform-grid free-space solution instead."""
