@@ -77,6 +77,13 @@ def lib():
         L.og_set_lambda.argtypes = [vp, d]
         L.og_set_axisymmetric.argtypes = [vp, ctypes.c_int]
         L.og_set_axisymmetric.restype = ctypes.c_int
+        L.og_last_coarse_exit.argtypes = [vp]
+        L.og_last_coarse_exit.restype = ctypes.c_int
+        L.og_set_coarse_stall.argtypes = [vp, ctypes.c_int]
+        L.og_coarse_solve.argtypes = [vp]
+        L.og_boundary_faces.argtypes = [vp, P(d), P(i32)]
+        L.og_boundary_faces.restype = i64
+        L.og_set_boundary_values.argtypes = [vp, P(d)]
         _lib = L
     return _lib
 
@@ -221,6 +228,40 @@ class OracleTree:
     @property
     def last_coarse_steps(self):
         return lib().og_last_coarse_steps(self._h)
+
+    EXIT_TARGET, EXIT_NMAX, EXIT_STALL = 0, 1, 2
+
+    @property
+    def last_coarse_exit(self):
+        return lib().og_last_coarse_exit(self._h)
+
+    def set_coarse_stall(self, steps):
+        """Stall window of the coarsest solve (default 8); 0: the paper's rule alone."""
+        lib().og_set_coarse_stall(self._h, int(steps))
+
+    def coarse_solve(self):
+        """The coarsest-grid solve alone (level 0, current v and f)."""
+        lib().og_coarse_solve(self._h)
+
+    def boundary_faces(self):
+        """(centres (n, 3), faces (n,)) of the physical Dirichlet faces of every level."""
+        n = int(lib().og_boundary_faces(self._h, None, None))
+        x = np.zeros((max(n, 1), 3))
+        f = np.zeros(max(n, 1), dtype=np.int32)
+        lib().og_boundary_faces(self._h, _dp(x), _ip(f))
+        return x[:n], f[:n]
+
+    def set_boundary_values(self, vals):
+        """Dirichlet values per listed face (order of boundary_faces())."""
+        n = int(lib().og_boundary_faces(self._h, None, None))
+        v = np.ascontiguousarray(vals, dtype=np.float64)
+        assert v.shape == (n,)
+        lib().og_set_boundary_values(self._h, _dp(v))
+
+    def set_boundary_function(self, fn):
+        """Dirichlet values from fn(centres (n, dim), faces (n,)) -> (n,)."""
+        x, f = self.boundary_faces()
+        self.set_boundary_values(fn(x[:, :self.dim], f))
 
     def face_gradient(self, phi, lam):
         phi, lam = self._leaf(phi), self._leaf(lam)

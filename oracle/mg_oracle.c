@@ -29,6 +29,7 @@ typedef struct {
     int has_children;
     int tested;      /* refinement predicate already evaluated */
     double *fld[NFIELD];
+    double *bval;    /* per-ghost Dirichlet values [face][a2][a1], or NULL: the face's constant */
 } OBlock;
 
 typedef struct {
@@ -59,6 +60,8 @@ struct og_tree {
     int *leaf;       /* leaf blocks in canonical order */
     int nleaf;
     int last_coarse_steps;
+    int last_coarse_exit;   /* OG_EXIT_TARGET, OG_EXIT_NMAX or OG_EXIT_STALL */
+    int stall_steps;        /* coarsest solve: stall window length, 0 = none */
     og_refine_fn refine;
     void *ud;
 };
@@ -237,6 +240,7 @@ og_tree *og_create(int dim, const int32_t *base_cells, const double *lo, const d
     }
     t->n_down = 2; t->n_up = 2; t->n_max = 1000; t->abs_tol = 0.0; t->rel_tol = 1e-8;
     t->smoother = OG_SMOOTH_GSRB; t->omega = 2.0 / 3.0; t->lambda = 0.0; t->axisym = 0;
+    t->stall_steps = STALL_STEPS;
     t->refine = refine; t->ud = ud;
 
     /* Added coarse grids (Sec. 2.5): halve the grid while every halved size still
@@ -346,8 +350,10 @@ og_tree *og_create(int dim, const int32_t *base_cells, const double *lo, const d
 
 void og_destroy(og_tree *t) {
     if (!t) return;
-    for (int i = 0; i < t->nblk; i++)
+    for (int i = 0; i < t->nblk; i++) {
         for (int f = 0; f < NFIELD; f++) free(t->blk[i].fld[f]);
+        free(t->blk[i].bval);
+    }
     for (int l = 0; l < t->nlev; l++) {
         free(t->lev[l].map);
         free(t->lev[l].list);
@@ -467,6 +473,8 @@ static void fill_ghosts_field(og_tree *t, int l, int field, int homogeneous) {
                                 u[gp] = ci;
                             } else {
                                 double a = homogeneous ? 0.0 : t->bc_val[face];
+                                if (!homogeneous && B->bval && t->bc_kind[face] == OG_DIRICHLET)
+                                    a = B->bval[(face * n2 + a2) * n1 + a1];
                                 if (t->bc_kind[face] == OG_DIRICHLET) u[gp] = 2.0 * a - ci;
                                 else u[gp] = ci + (side ? 1.0 : -1.0) * L->h[d] * a;
                             }
@@ -508,6 +516,73 @@ static void fill_ghosts_field(og_tree *t, int l, int field, int homogeneous) {
             }
         }
     }
+}
+
+/* Dirichlet values that vary along a face (Sec. 2.6: the ghost of a boundary cell is
+ * 2a - phi_i with a the value at the centre of the cell's boundary face), on every
+ * level.  The faces are enumerated level by level (coarsest first), then blocks in
+ * creation order, then faces -x..+z, then the face's cells (lower in-plane axis
+ * fastest); only faces on a physical Dirichlet boundary are listed.  With centres
+ * (3 per face) and faces non-NULL the positions and face indices are written. */
+int64_t og_boundary_faces(const og_tree *t, double *centres, int32_t *faces) {
+    int64_t n = 0;
+    for (int l = 0; l < t->nlev; l++) {
+        const OLevel *L = &t->lev[l];
+        for (int q = 0; q < L->n; q++) {
+            const OBlock *B = &t->blk[L->list[q]];
+            for (int d = 0; d < t->dim; d++) {
+                int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+                int n1 = ext(t, l, t1), n2 = ext(t, l, t2);
+                for (int side = 0; side < 2; side++) {
+                    int face = 2 * d + side;
+                    if (t->bc_kind[face] != OG_DIRICHLET) continue;
+                    int gd = side ? B->org[d] + L->bs : B->org[d] - 1;
+                    if (gd >= 0 && gd < L->ncell[d]) continue;   /* not on the boundary */
+                    for (int a2 = 0; a2 < n2; a2++)
+                        for (int a1 = 0; a1 < n1; a1++) {
+                            if (centres) {
+                                double *x = centres + 3 * n;
+                                x[d] = side ? t->hi[d] : t->lo[d];
+                                x[t1] = t->lo[t1] + (B->org[t1] + a1 + 0.5) * L->h[t1];
+                                x[t2] = t->dim == 3 ? t->lo[t2] + (B->org[t2] + a2 + 0.5) * L->h[t2] : 0.0;
+                            }
+                            if (faces) faces[n] = face;
+                            n++;
+                        }
+                }
+            }
+        }
+    }
+    return n;
+}
+
+/* Values for the faces listed by og_boundary_faces, in that order; they replace the
+ * face's constant value on every level. */
+void og_set_boundary_values(og_tree *t, const double *vals) {
+    int64_t n = 0;
+    for (int l = 0; l < t->nlev; l++) {
+        const OLevel *L = &t->lev[l];
+        for (int q = 0; q < L->n; q++) {
+            OBlock *B = &t->blk[L->list[q]];
+            for (int d = 0; d < t->dim; d++) {
+                int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+                int n1 = ext(t, l, t1), n2 = ext(t, l, t2);
+                for (int side = 0; side < 2; side++) {
+                    int face = 2 * d + side;
+                    if (t->bc_kind[face] != OG_DIRICHLET) continue;
+                    int gd = side ? B->org[d] + L->bs : B->org[d] - 1;
+                    if (gd >= 0 && gd < L->ncell[d]) continue;
+                    if (!B->bval) {
+                        B->bval = (double *)malloc((size_t)2 * t->dim * n1 * n2 * sizeof(double));
+                        for (int f = 0; f < 2 * t->dim * n1 * n2; f++) B->bval[f] = 0.0;
+                    }
+                    for (int a2 = 0; a2 < n2; a2++)
+                        for (int a1 = 0; a1 < n1; a1++) B->bval[(face * n2 + a2) * n1 + a1] = vals[n++];
+                }
+            }
+        }
+    }
+    for (int l = 0; l < t->nlev; l++) og_fill_ghosts_level(t, l);
 }
 
 void og_fill_ghosts_level(og_tree *t, int l) {
@@ -776,19 +851,30 @@ static void coarse_solve(og_tree *t) {
     double r0 = level_residual_max(t, 0), best = r0;
     double target = t->abs_tol > t->rel_tol * r0 ? t->abs_tol : t->rel_tol * r0;
     int k, since = 0;
+    t->last_coarse_exit = OG_EXIT_NMAX;
     for (k = 1; k <= t->n_max; k++) {
         smooth_step(t, 0);
         double r = level_residual_max(t, 0);
-        if (r <= target) break;
+        if (r <= target) {
+            t->last_coarse_exit = OG_EXIT_TARGET;
+            break;
+        }
         if (r < STALL * best) {
             best = r;
             since = 0;
-        } else if (++since >= STALL_STEPS) {
+        } else if (t->stall_steps > 0 && ++since >= t->stall_steps) {
+            t->last_coarse_exit = OG_EXIT_STALL;
             break;
         }
     }
     t->last_coarse_steps = k > t->n_max ? t->n_max : k;
 }
+
+int og_last_coarse_exit(const og_tree *t) { return t->last_coarse_exit; }
+
+void og_coarse_solve(og_tree *t) { coarse_solve(t); }
+
+void og_set_coarse_stall(og_tree *t, int steps) { t->stall_steps = steps > 0 ? steps : 0; }
 
 int og_last_coarse_steps(const og_tree *t) { return t->last_coarse_steps; }
 

@@ -75,8 +75,23 @@ void og_residual_norm(og_tree *t, double *max_rel, double *l2_rel);
 void og_leaf_residual(og_tree *t, double *leaf_r);
 /* Composite operator L(phi) on leaves for the given leaf phi (overwrites phi state). */
 void og_apply(og_tree *t, const double *leaf_phi, double *leaf_out);
-/* Steps taken by the last coarsest-grid solve. */
+/* Steps taken by the last coarsest-grid solve, and why it stopped: the tolerance was
+ * met, n_max steps were taken, or the stall window ended it. */
 int og_last_coarse_steps(const og_tree *t);
+enum { OG_EXIT_TARGET = 0, OG_EXIT_NMAX = 1, OG_EXIT_STALL = 2 };
+int og_last_coarse_exit(const og_tree *t);
+/* Length of the coarsest solve's stall window (default 8 steps); 0 removes it, which
+ * leaves the paper's rule alone (tolerance or n_max). */
+void og_set_coarse_stall(og_tree *t, int steps);
+/* The coarsest-grid solve alone, on the current v and f of level 0. */
+void og_coarse_solve(og_tree *t);
+
+/* Face-varying Dirichlet values (Sec. 2.6): the physical Dirichlet faces of every
+ * block of every level, with their centres (3 doubles each, may be NULL) and face
+ * indices (may be NULL); returns the count.  og_set_boundary_values takes one value
+ * per listed face, used by the ghost 2a - phi_i in place of the face's constant. */
+int64_t og_boundary_faces(const og_tree *t, double *centres, int32_t *faces);
+void og_set_boundary_values(og_tree *t, const double *vals);
 
 /* Adjoint pieces: dJ/deps per leaf cell given the state phi and the adjoint lambda.
  * Uniform trees only (all leaves on one level); returns -1 otherwise. */

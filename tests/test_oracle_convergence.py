@@ -13,7 +13,7 @@ from paper_1901_11370_amd import workloads as W
 
 def _errors(grid, iters=2):
     w = W.x1(grid, base=64)
-    o = oracle_trees(w)[0]
+    o = oracle_trees(w)[0]    # boundary values of the solution in the ghosts
     lay = o.leaf_layout()
     o.set_rhs(w.rhs(0, lay))
     d = w.domains[0]
