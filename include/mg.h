@@ -124,7 +124,13 @@ int mg_default_params(mg_params *p);
 /* Builds the tree(s) on the host.  block_size must be 4, 8 or 16; every domain's
  * base_cells must be multiples of it.  max_refine_levels >= 0 limits refinement
  * above the base grid.  Returns MG_ERR_ARG for invalid input (also for a domain that
- * does not meet the requirements of params->axisymmetric when that is set). */
+ * does not meet the requirements of params->axisymmetric when that is set).
+ * Singular problems: with helmholtz_lambda = 0 a domain without a Dirichlet face has
+ * constants in the operator's null space.  A fully periodic domain is accepted (its
+ * coarsest grid subtracts the mean of f, so the solution is defined up to a constant);
+ * a domain whose faces are all Neumann, or Neumann and periodic, is rejected with
+ * MG_ERR_ARG (balancing the boundary fluxes against f is not part of the method of
+ * Sec. 2.6).  With helmholtz_lambda > 0 every combination of kinds is regular. */
 int mg_tree_create(const mg_domain *domains, int n_domains, int block_size,
                    int max_refine_levels, mg_refine_fn refine, void *user_data,
                    const mg_params *params, mg_tree **out);
@@ -160,6 +166,42 @@ int mg_set_rhs(mg_tree *t, const double *leaf_f, int on_device);
 int mg_set_eps(mg_tree *t, const double *leaf_eps, int on_device);
 int mg_set_phi(mg_tree *t, const double *leaf_phi, int on_device);
 int mg_get_phi(mg_tree *t, double *leaf_phi, int on_device);
+
+/* The composite operator of Sec. 2.2 applied to a leaf array: leaf_out = L phi
+ * (div(eps grad phi) - lambda phi with the tree's eps and boundary values, or zero
+ * boundary values after mg_set_homogeneous_bc), evaluated as the residual is: parents
+ * take the mean of their children, ghosts are filled coarse to fine, then the stencil
+ * runs on the leaves.  leaf_phi and leaf_out are leaf arrays (host, or device with
+ * on_device = 1; they must not overlap).  The tree's phi and f are unchanged; the
+ * v_old field, which only carries values within a cycle, is used as scratch.
+ * Asynchronous for device pointers; synchronises for host pointers. */
+int mg_apply_operator(mg_tree *t, const double *leaf_phi, double *leaf_out, int on_device);
+
+/* Dirichlet values that vary along a face (Sec. 2.6; e.g. the boundary values of the
+ * analytic solution in the convergence test of Sec. 3.1).
+ *
+ * mg_boundary_faces lists the leaf-cell faces that lie on a physical Dirichlet face:
+ * face direction by direction (-x, +x, -y, +y, -z, +z), within a direction the leaf
+ * blocks in leaf order, within a block the bs^(d-1) cells of that face with the lower
+ * in-plane axis fastest.  n_faces receives the count; leaf_cell (the leaf index of the
+ * cell, may be NULL) and face (its face, 0..5, may be NULL) receive n_faces entries.
+ *
+ * mg_fold_dirichlet takes one value a per listed face, in that order (host, or device
+ * with on_device = 1), and folds them into the current right-hand side: the leaf
+ * equations with these Dirichlet ghosts (2a - phi_b at a boundary face) differ from
+ * the equations with the tree's own ghosts by a constant per cell, f is shifted by it,
+ * and the solve keeps the tree's own ghosts (value from mg_domain, normally 0) on every
+ * level.  The shift is the composite operator applied to phi = 0 with the values in
+ * the physical ghosts of the leaf blocks: eps_b 2a/h^2 for a boundary cell (h its
+ * spacing across the face) and, where a coarse-fine face meets the boundary, the
+ * change of the interpolated ghost through the coarse cell's boundary ghost.  The
+ * solution then solves the leaf problem with the given face values exactly (they add
+ * to the face's mg_domain value).  Call after mg_set_rhs (and mg_set_eps); folding
+ * twice adds twice; mg_set_rhs restores a plain right-hand side.  Uses the staging
+ * buffers and the v_old field as scratch (MG_ERR_ARG if 6 x blocks, plus the values
+ * when they are on the host, exceed the leaf cells) and synchronises the stream. */
+int mg_boundary_faces(const mg_tree *t, int64_t *n_faces, int64_t *leaf_cell, int32_t *face);
+int mg_fold_dirichlet(mg_tree *t, const double *values, int on_device);
 
 /* Treat every Dirichlet/Neumann value as 0 (on != 0) -- used for adjoint solves. */
 int mg_set_homogeneous_bc(mg_tree *t, int on);
@@ -254,7 +296,8 @@ int mg_freespace_values(const mg_tree *t, int64_t *n_values);
  * free-space solution; this cheaper guess serves the same purpose: near the boundary
  * it already matches the folded values, so FMG's coarse problems are consistent there
  * (from phi = 0 they see a boundary forcing that doubles per level).  Uses the staging
- * buffers and synchronises the stream. */
+ * buffers and synchronises the stream.  Returns MG_ERR_STATE if boundary values were
+ * folded into f (mg_freespace_bc, mg_fold_dirichlet) since the last mg_set_rhs. */
 int mg_freespace_guess(mg_tree *t, int coarsen);
 
 /* Kernel timing: when enabled, HIP events bracket every launch of the smoothing

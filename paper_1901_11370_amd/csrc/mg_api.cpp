@@ -31,6 +31,7 @@ struct mg_tree {
     hipStream_t stream = nullptr;
     bool bound = false;
     bool homog = false;
+    bool folded = false;            // boundary values folded into f since the last mg_set_rhs
     // device views
     DevTables tb{}, tb0{};          // real boundary values / homogeneous
     uint64_t tail_lds[2] = {0, 0};  // domains whose coarse grids fit in LDS (FP64, FP32)
@@ -856,6 +857,24 @@ int mg_tree_create(const mg_domain *domains, int n_domains, int block_size, int 
                 return MG_ERR_ARG;
             }
     }
+    if (domains && p.helmholtz_lambda == 0.0) {
+        // Without a Dirichlet face the operator annihilates constants.  A fully periodic
+        // domain is made consistent on its coarsest grid (the mean of f is removed); a
+        // domain whose faces are Neumann, or Neumann and periodic, would need its
+        // boundary fluxes balanced against f, which the paper does not describe: rejected.
+        for (int i = 0; i < n_domains; i++) {
+            const int nf = domains[i].dim == 2 ? 4 : 6;
+            bool dirichlet = false, periodic = true;
+            for (int f = 0; f < nf && f < 6; f++) {
+                dirichlet = dirichlet || domains[i].bc.kind[f] == MG_BC_DIRICHLET;
+                periodic = periodic && domains[i].bc.kind[f] == MG_BC_PERIODIC;
+            }
+            if (!dirichlet && !periodic) {
+                delete t;
+                return MG_ERR_ARG;
+            }
+        }
+    }
     std::string e = build_tree(t->T, domains, n_domains, block_size, max_refine_levels, refine, user_data);
     if (!e.empty()) {
         delete t;
@@ -906,6 +925,7 @@ int mg_tree_bind(mg_tree *t, void *device_store, size_t bytes, void *hip_stream)
                                   t->stream));
     t->bound = true;
     t->homog = false;
+    t->folded = false;
     // phi = 0, f = 0, eps = 1 everywhere; ghosts of the block levels filled.
     Launch L = launch(t, false);
     auto init = [&](auto &P, auto one) {
@@ -1000,6 +1020,7 @@ int mg_set_rhs(mg_tree *t, const double *leaf_f, int on_device) {
     const double *src = stage_in(t, leaf_f, on_device, t->d_stage, &rc);
     if (rc) return rc;
     K<double>::scatter(launch(t, false), t->P64.f, src, (int)t->nleafblk);
+    t->folded = false;
     return check_launch(t);
 }
 
@@ -1038,6 +1059,123 @@ int mg_get_phi(mg_tree *t, double *leaf_phi, int on_device) {
         HIP_OR_FAIL(t, hipMemcpyAsync(leaf_phi, dst, (size_t)t->T.nleaf_cells * 8, hipMemcpyDeviceToHost, t->stream));
         HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));
     }
+    return MG_OK;
+}
+
+int mg_apply_operator(mg_tree *t, const double *leaf_phi, double *leaf_out, int on_device) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!leaf_phi || !leaf_out) return MG_ERR_ARG;
+    const double *src = stage_in(t, leaf_phi, on_device, t->d_stage, &rc);
+    if (rc) return rc;
+    // phi goes into the FP64 v_old field (scratch between cycles: every restriction
+    // rewrites it before a correction reads it); the tree's phi is not touched
+    Plane<double> Q = t->P64;
+    Q.v = t->P64.vold;
+    Q.vg = t->P64.voldg;
+    Q.f = nullptr;
+    Driver<double> D{t, launch(t, t->homog), Q, var(t)};
+    K<double>::scatter(D.L, Q.v, src, (int)t->nleafblk);
+    if (t->T.refined) D.sync();
+    else
+        for (int l = t->T.nt; l < t->T.nlev; l++) D.ghost_level(l, all_mask(t));
+    // L phi as a rank-major leaf vector, back into the leaf blocks, then leaf order
+    launch_norm64(D.L, Q, (int)t->nleafblk, var(t), nullptr, t->d_stage2);
+    launch_vec_blocks<double>(D.L, Q.v, t->d_stage2, (int)t->nleafblk, true);
+    double *dst = on_device ? leaf_out : t->d_stage;
+    K<double>::gather(D.L, Q.v, dst, (int)t->nleafblk);
+    if ((rc = check_launch(t))) return rc;
+    if (!on_device) {
+        HIP_OR_FAIL(t, hipMemcpyAsync(leaf_out, dst, (size_t)t->T.nleaf_cells * 8, hipMemcpyDeviceToHost, t->stream));
+        HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));
+    }
+    return MG_OK;
+}
+
+// Leaf blocks (in leaf order, as leaf ranks) whose face `face` lies on a physical
+// Dirichlet boundary.
+static std::vector<int32_t> dirichlet_face_ranks(const mg_tree *t, int face) {
+    const HostTree &T = t->T;
+    std::vector<int32_t> out;
+    for (size_t r = 0; r < T.leaf_blk.size(); r++) {
+        const int b = T.leaf_blk[r];
+        if (T.nbr[6 * (size_t)b + face] == -1 && T.doms[T.dom[b]].d.bc.kind[face] == MG_BC_DIRICHLET)
+            out.push_back((int32_t)r);
+    }
+    return out;
+}
+
+int mg_boundary_faces(const mg_tree *t, int64_t *n_faces, int64_t *leaf_cell, int32_t *face) {
+    if (!t || !n_faces) return MG_ERR_ARG;
+    const HostTree &T = t->T;
+    const int bs = T.bs, nf = T.dim == 3 ? bs * bs : bs;
+    const int64_t nc = T.dim == 3 ? (int64_t)bs * bs * bs : (int64_t)bs * bs;
+    int64_t n = 0;
+    for (int f = 0; f < 2 * T.dim; f++) {
+        const int a = f / 2, c = (f & 1) ? bs - 1 : 0;
+        for (int32_t r : dirichlet_face_ranks(t, f)) {
+            for (int q = 0; q < nf; q++, n++) {
+                if (!leaf_cell && !face) continue;
+                const int a1 = q % bs, a2 = T.dim == 3 ? q / bs : 0;
+                const int i = a == 0 ? c : a1, j = a == 1 ? c : (a == 0 ? a1 : a2), k = a == 2 ? c : a2;
+                if (leaf_cell) leaf_cell[n] = (int64_t)r * nc + ((int64_t)k * bs + j) * bs + i;
+                if (face) face[n] = f;
+            }
+        }
+    }
+    *n_faces = n;
+    return MG_OK;
+}
+
+int mg_fold_dirichlet(mg_tree *t, const double *values, int on_device) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!values) return MG_ERR_ARG;
+    const HostTree &T = t->T;
+    const int nf = T.dim == 3 ? T.bs * T.bs : T.bs;
+    // per block and face the offset of its values in the list (leaf blocks on a
+    // Dirichlet face), -1 elsewhere
+    std::vector<int64_t> off(6 * (size_t)t->nb, -1);
+    int64_t nv = 0;
+    for (int f = 0; f < 2 * T.dim; f++)
+        for (int32_t r : dirichlet_face_ranks(t, f)) {
+            off[6 * (size_t)T.leaf_blk[r] + f] = nv;
+            nv += nf;
+        }
+    // scratch: the offset table (and host values) in the first staging buffer, L_a(0) in
+    // the second, the zero field in v_old
+    const int64_t words = 6 * t->nb + (on_device ? 0 : nv);
+    if (words > T.nleaf_cells) return fail(t, MG_ERR_ARG, "grid too small for the boundary-value scratch");
+    int64_t *d_off = reinterpret_cast<int64_t *>(t->d_stage);
+    HIP_OR_FAIL(t, hipMemcpyAsync(d_off, off.data(), off.size() * 8, hipMemcpyHostToDevice, t->stream));
+    const double *d_val = values;
+    if (!on_device) {
+        double *dst = t->d_stage + 6 * t->nb;
+        if (nv) HIP_OR_FAIL(t, hipMemcpyAsync(dst, values, (size_t)nv * 8, hipMemcpyHostToDevice, t->stream));
+        d_val = dst;
+    }
+    // The shift of the leaf equations is the composite operator applied to phi = 0 with
+    // these values in the physical ghosts (2a at a Dirichlet face) and zero elsewhere:
+    // the boundary cells' 2a eps/h^2 terms and, where a coarse-fine face meets the
+    // boundary, the change of the interpolated ghost through the coarse cell's
+    // boundary ghost.  It is computed by the ghost and stencil kernels themselves.
+    Plane<double> Q = t->P64;
+    Q.v = t->P64.vold;
+    Q.vg = t->P64.voldg;
+    Q.f = nullptr;
+    // (homogeneous tables: every face without listed values contributes nothing)
+    Driver<double> D{t, launch(t, true), Q, var(t)};
+    D.L.tb.fv_off = d_off;
+    D.L.tb.fv = d_val;
+    K<double>::zero(D.L, Q.v, (size_t)(t->nb * t->nc));
+    K<double>::zero(D.L, Q.vg, (size_t)(t->nb * t->ng));
+    for (int l = T.nt; l < T.nlev; l++) D.ghost_level(l, all_mask(t));
+    launch_norm64(D.L, Q, (int)t->nleafblk, var(t), nullptr, t->d_stage2);
+    launch_sub_vec_blocks(D.L, t->P64.f, t->d_stage2, (int)t->nleafblk);
+    if ((rc = check_launch(t))) return rc;
+    t->folded = true;
+    // the host offset table (and host values) must outlive the copies
+    HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));
     return MG_OK;
 }
 
@@ -1240,6 +1378,7 @@ int mg_divb_rhs(mg_tree *t, const double *leaf_B, int order, int on_device) {
         launch_divb(L, src, t->d_stage2, d, d > 0, order, n);
     }
     K<double>::scatter(L, t->P64.f, t->d_stage2, (int)t->nleafblk);
+    t->folded = false;
     if ((rc = check_launch(t))) return rc;
     if (!on_device) HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));   // the host buffer may be reused
     return MG_OK;
@@ -1352,6 +1491,7 @@ int mg_freespace_bc(mg_tree *t, int coarsen, double *bvals, int on_device) {
     launch_freespace(launch(t, false), t->P64.f, dfd, T.ndom, max_pts, ptot, c, slices, q, partial, pl, bv,
                      (int)t->nleafblk);
     if ((rc = check_launch(t))) return rc;
+    t->folded = true;
     if (bvals && !on_device)
         HIP_OR_FAIL(t, hipMemcpyAsync(bvals, bst, (size_t)btot * 8, hipMemcpyDeviceToHost, t->stream));
     HIP_OR_FAIL(t, hipStreamSynchronize(t->stream));   // the domain table lives on this stack
@@ -1364,6 +1504,9 @@ int mg_freespace_guess(mg_tree *t, int coarsen) {
     int max_pts;
     int rc = fs_setup(t, coarsen, fd, qtot, ptot, btot, max_pts);
     if (rc) return rc;
+    if (t->folded)
+        return fail(t, MG_ERR_STATE, "the far-field guess needs the plain right-hand side: call it before the "
+                                     "boundary values are folded into f (or set f again)");
     const HostTree &T = t->T;
     const int64_t n = T.nleaf_cells;
     const int64_t fd_words = ((int64_t)sizeof(FsDom) * T.ndom + 7) / 8;

@@ -38,6 +38,11 @@ struct DevTables {
     double lambda;            // Helmholtz term: L phi = div(eps grad phi) - lambda phi
     int axi;                  // 2D axisymmetric form (x = r): r-face factors on the x faces
     const double *lox;        // [ndom] lower x bound (the radius of the domain's inner face)
+    // Per-cell Dirichlet values of physical faces (only while boundary values are folded
+    // into f; null otherwise): fv_off[6 b + f] is the offset in fv of block b's face f
+    // (bs^(d-1) values, lower in-plane axis fastest), or -1 for the domain's constant.
+    const int64_t *fv_off;
+    const double *fv;
 };
 
 // Tail levels with more cells than this (per domain) run as multi-workgroup launches;
@@ -148,6 +153,8 @@ void launch_add_leaf(const Launch &L, double *v64, double *vg64, const float *v3
 void launch_add_vec(const Launch &L, double *v64, double *vg64, const double *vec, int nleafblk);
 template <typename S>
 void launch_vec_blocks(const Launch &L, S *blk, double *vec, int nleafblk, bool to_blocks);
+// blk -= vec on the leaf blocks (FP64; vec rank-major as above).
+void launch_sub_vec_blocks(const Launch &L, double *blk, const double *vec, int nleafblk);
 int dots_chunks(int64_t n);
 // out[i] = <V_i, w> for i < k (V_i = V + i * stride); partial holds k * dots_chunks(n).
 void launch_dots(const Launch &L, const double *V, int64_t stride, int k, const double *w, int64_t n,

@@ -559,7 +559,12 @@ __device__ void ghost_cell(const Plane<T> &P, const DevTables &tb, int64_t b, in
             out = ci;
         } else {
             const double *hh = tb.h + ((size_t)dm * MAXLEV + tb.lev[b]) * 3;
-            out = bc_ghost<T>(tb.bck[6 * dm + f], tb.bcv[6 * dm + f], hh[a], side, ci);
+            double bv = tb.bcv[6 * dm + f];
+            if (tb.fv_off) {
+                const int64_t o = tb.fv_off[6 * b + f];
+                if (o >= 0) bv = tb.fv[o + (D == 3 ? a2 * BS : 0) + a1];
+            }
+            out = bc_ghost<T>(tb.bck[6 * dm + f], bv, hh[a], side, ci);
         }
     } else {
         const int dm = tb.dom[b];
@@ -2398,6 +2403,15 @@ __global__ void __launch_bounds__(256) k_vec_blocks(S *blk, double *vec, DevTabl
     else vec[rank * g::NC + t] = (double)blk[b * g::NC + t];
 }
 
+__global__ void __launch_bounds__(256) k_sub_vec_blocks(double *blk, const double *vec, DevTables tb, int nc,
+                                                        int wg_per_block) {
+    const int64_t rank = blockIdx.x / wg_per_block;
+    const int t = (blockIdx.x % wg_per_block) * (nc < 256 ? nc : 256) + threadIdx.x;
+    if (t >= nc) return;
+    const int64_t b = tb.leaf_blk[rank];
+    blk[b * nc + t] -= vec[rank * nc + t];
+}
+
 constexpr int kChunk = 4096;   // vector elements per workgroup of the inner products
 
 // partial[i * nchunk + c] = sum over chunk c of V_i[x] w[x] for i < k (V_i = V + i stride).
@@ -2863,6 +2877,12 @@ void launch_vec_blocks(const Launch &L, S *blk, double *vec, int nleafblk, bool 
         if (to_blocks) k_vec_blocks<S, D, BS, true><<<nb, TPB, 0, L.stream>>>(blk, vec, L.tb, NC / TPB);
         else k_vec_blocks<S, D, BS, false><<<nb, TPB, 0, L.stream>>>(blk, vec, L.tb, NC / TPB);
     });
+}
+void launch_sub_vec_blocks(const Launch &L, double *blk, const double *vec, int nleafblk) {
+    if (nleafblk <= 0) return;
+    const int nc = cells(L.dim, L.bs);
+    const int tpb = nc < 256 ? nc : 256;
+    k_sub_vec_blocks<<<(unsigned)(nleafblk * (nc / tpb)), tpb, 0, L.stream>>>(blk, vec, L.tb, nc, nc / tpb);
 }
 template void launch_vec_blocks<float>(const Launch &, float *, double *, int, bool);
 template void launch_vec_blocks<double>(const Launch &, double *, double *, int, bool);

@@ -75,6 +75,9 @@ _SIGS = {
     "mg_set_phi": ([_vp, _vp, ctypes.c_int], ctypes.c_int),
     "mg_get_phi": ([_vp, _vp, ctypes.c_int], ctypes.c_int),
     "mg_set_homogeneous_bc": ([_vp, ctypes.c_int], ctypes.c_int),
+    "mg_apply_operator": ([_vp, _vp, _vp, ctypes.c_int], ctypes.c_int),
+    "mg_boundary_faces": ([_vp, _P(_i64), _P(_i64), _P(_i32)], ctypes.c_int),
+    "mg_fold_dirichlet": ([_vp, _vp, ctypes.c_int], ctypes.c_int),
     "mg_vcycle": ([_vp, ctypes.c_int], ctypes.c_int),
     "mg_fmg": ([_vp, ctypes.c_int], ctypes.c_int),
     "mg_residual_norm": ([_vp, _P(_d), _P(_d)], ctypes.c_int),
@@ -256,6 +259,46 @@ class Tree:
         a = np.zeros(self.n_leaf)
         _check(mg_get_phi(self.h, a.ctypes.data_as(_vp), 0), self.h)
         return a
+
+    def apply_operator(self, phi, out=None):
+        """L phi on the leaves (composite operator, the tree's eps and boundary values).
+        phi a CUDA tensor: the result is a CUDA tensor (``out`` if given); else numpy."""
+        p, dev, keep = self._arg(phi)
+        if dev:
+            import torch
+            o = out if out is not None else torch.empty(self.n_leaf, dtype=torch.float64, device=self.store.device)
+            _check(mg_apply_operator(self.h, p, _vp(o.data_ptr()), 1), self.h)
+            return o
+        o = np.zeros(self.n_leaf)
+        _check(mg_apply_operator(self.h, p, o.ctypes.data_as(_vp), 0), self.h)
+        return o
+
+    def boundary_faces(self):
+        """(leaf_cell, face) of every leaf-cell face on a physical Dirichlet face, in the
+        order mg_fold_dirichlet takes its values."""
+        n = _i64()
+        _check(mg_boundary_faces(self.h, ctypes.byref(n), None, None), self.h)
+        cells = np.zeros(n.value, dtype=np.int64)
+        faces = np.zeros(n.value, dtype=np.int32)
+        _check(mg_boundary_faces(self.h, ctypes.byref(n), cells.ctypes.data_as(_P(_i64)),
+                                 faces.ctypes.data_as(_P(_i32))), self.h)
+        return cells, faces
+
+    def fold_dirichlet(self, values):
+        """f_b -= 2 a / h^2 for the face values a (order of boundary_faces())."""
+        p, dev, keep = self._arg_n(values)
+        _check(mg_fold_dirichlet(self.h, p, dev), self.h)
+
+    def _arg_n(self, a):
+        """(pointer, on_device, keepalive) for an array of any length."""
+        import torch
+        if isinstance(a, torch.Tensor) and a.is_cuda:
+            a = a.detach().to(torch.float64).contiguous()
+            return _vp(a.data_ptr()), 1, a
+        if isinstance(a, torch.Tensor):
+            a = a.detach().numpy()
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        return a.ctypes.data_as(_vp), 0, a
 
     def set_homogeneous_bc(self, on: bool):
         _check(mg_set_homogeneous_bc(self.h, 1 if on else 0), self.h)

@@ -49,6 +49,19 @@ def cell_widths(layout: np.ndarray, dom: Domain) -> np.ndarray:
     return np.stack([(dom.hi[d] - dom.lo[d]) / dom.base_cells[d] / scale for d in range(dom.dim)], axis=1)
 
 
+def face_centres(layout: np.ndarray, dom: Domain, faces: np.ndarray) -> np.ndarray:
+    """(n, dim) centres of face `faces[i]` (0..2 dim - 1: -x, +x, -y, ...) of the cells
+    listed in an integer layout (level, I, J, K)."""
+    x = cell_centres(layout, dom)
+    w = cell_widths(layout, dom)
+    faces = np.asarray(faces)
+    for a in range(dom.dim):
+        on = faces // 2 == a
+        sgn = np.where(faces[on] % 2 == 1, 0.5, -0.5)
+        x[on, a] += sgn * w[on, a]
+    return x
+
+
 def block_centres(dom: Domain, level: int, origin, bs: int) -> np.ndarray:
     """Centres of the bs^d cells of a block given its level (above base) and origin."""
     ax = []
@@ -94,6 +107,9 @@ class Workload:
     rhs: Optional[Callable] = None      # rhs(domain_index, layout) -> f
     eps: Optional[Callable] = None      # eps(domain_index, layout) -> eps
     target: Optional[Callable] = None
+    # dirichlet(domain_index, face centres (n, dim)) -> values of a Dirichlet boundary
+    # that varies along the faces (None: the domains' constant face values)
+    dirichlet: Optional[Callable] = None
     note: str = ""
 
 
@@ -249,15 +265,9 @@ def x1_laplacian(x: np.ndarray) -> np.ndarray:
 def x1(grid: str = "uniform", base: int = 64) -> Workload:
     """The paper's convergence test (Sec. 3.1): unit cube centred at the origin,
     lap(phi) = f with f the analytic Laplacian of x1_solution and Dirichlet values
-    from the solution.  grid: 'uniform' (base^3), 'center' or 'corner' (two extra
-    levels covering 0.5^3 and 0.25^3, each again base^3 cells, centred at the origin
-    or around (-0.25, -0.25, -0.25)).
-
-    The library takes one Dirichlet value per face, so the varying boundary values
-    enter through the right-hand side: with the reflection ghost g = 2b - phi_i the
-    equation of a boundary cell equals the one with g = -phi_i (homogeneous value) and
-    f - 2 b / h^2 per boundary face (b = phi_sol at the face centre).  The discrete
-    problem and its residual at every leaf cell are the same."""
+    from the solution at the boundary face centres (``dirichlet``).  grid: 'uniform'
+    (base^3), 'center' or 'corner' (two extra levels covering 0.5^3 and 0.25^3, each
+    again base^3 cells, centred at the origin or around (-0.25, -0.25, -0.25))."""
     dom = Domain(3, [base] * 3, [-0.5] * 3, [0.5] * 3, [DIRICHLET] * 6)
     if grid == "center":
         boxes = {0: (-0.25, 0.25), 1: (-0.125, 0.125)}
@@ -274,20 +284,10 @@ def x1(grid: str = "uniform", base: int = 64) -> Workload:
         return all(lo - 1e-12 <= -0.5 + origin[q] * h and -0.5 + (origin[q] + bs) * h <= hi + 1e-12
                    for q in range(3))
 
-    def rhs(i, lay):
-        x = cell_centres(lay, dom)
-        h = cell_widths(lay, dom)
-        f = x1_laplacian(x)
-        for a in range(3):
-            for side, face in ((0, -0.5), (1, 0.5)):
-                on = np.isclose(x[:, a] + (h[:, a] / 2 if side else -h[:, a] / 2), face)
-                xb = x[on].copy()
-                xb[:, a] = face
-                f[on] -= 2.0 * x1_solution(xb) / h[on, a] ** 2
-        return f
-
     return Workload(f"convergence_{grid}_{base}", [dom], max_refine=len(boxes), refine=rule if boxes else None,
-                    rhs=rhs, note="phi_sol = cos(pi n.x) + 10 exp(-100|x|^2), n = (1,2,3)")
+                    rhs=lambda i, lay: x1_laplacian(cell_centres(lay, dom)),
+                    dirichlet=lambda i, xf: x1_solution(xf),
+                    note="phi_sol = cos(pi n.x) + 10 exp(-100|x|^2), n = (1,2,3)")
 
 
 # ------------------------------------------------ divergence cleaning (Sec. 4)

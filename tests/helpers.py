@@ -10,13 +10,31 @@ def gpu_domain(mg, d):
 
 
 def oracle_trees(w, **kw):
+    """Reference trees of a workload; face-varying Dirichlet values (w.dirichlet) go into
+    the reference's ghost cells on every level."""
     from oracle import OracleTree
     out = []
     for i, d in enumerate(w.domains):
-        out.append(OracleTree(d.dim, d.base_cells, d.lo, d.hi, d.bc_kind, bc_value=list(d.bc_value), bs=w.bs,
-                              max_refine=w.max_refine, refine=w.refine, domain_id=i,
-                              variable_eps=w.variable_eps, **kw))
+        o = OracleTree(d.dim, d.base_cells, d.lo, d.hi, d.bc_kind, bc_value=list(d.bc_value), bs=w.bs,
+                       max_refine=w.max_refine, refine=w.refine, domain_id=i,
+                       variable_eps=w.variable_eps, **kw)
+        if w.dirichlet is not None:
+            o.set_boundary_function(lambda x, f, i=i: w.dirichlet(i, x))
+        out.append(o)
     return out
+
+
+def fold_dirichlet(w, t):
+    """Face-varying Dirichlet values of a workload into the GPU tree's current
+    right-hand side (mg_fold_dirichlet), evaluated at the leaf face centres."""
+    cells, faces = t.boundary_faces()
+    lay = t.leaf_layout()
+    vals = np.empty(len(cells))
+    for i, d in enumerate(w.domains):
+        on = lay[cells, 0] == i
+        xf = W.face_centres(lay[cells[on], 1:], d, faces[on])
+        vals[on] = w.dirichlet(i, xf)
+    t.fold_dirichlet(vals)
 
 
 def gpu_tree(w, bind=True, **params):

@@ -123,3 +123,39 @@ def test_zero_problem_stays_zero():
     assert (c, rc) == (0, mg.MG_OK)
     c, rc = t.solve(rel_tol=1e-10, max_cycles=5)   # the FP64 FMG runs before the first check
     assert (c, rc) == (1, mg.MG_OK) and np.all(t.get_phi() == 0.0)
+
+
+@pytest.mark.parametrize("homogeneous", [False, True])
+def test_apply_operator_matches_reference(homogeneous):
+    # L phi for a random phi on a refined 3D tree with variable eps and every boundary
+    # kind with non-zero values (periodic in y), against the reference operator
+    dom = W.Domain(3, [32, 32, 48], [0.0, 0.0, 0.0], [1.0, 1.0, 1.5],
+                   [W.DIRICHLET, W.NEUMANN, W.PERIODIC, W.PERIODIC, W.NEUMANN, W.DIRICHLET],
+                   [0.7, -0.3, 0.0, 0.0, 0.4, -1.1])
+
+    def refine(d, level, origin, bs):
+        return level == 0 and origin[0] >= 16 and origin[2] < 32
+
+    w = W.Workload("apply_op", [dom], bs=16, max_refine=1, refine=refine, variable_eps=True,
+                   eps=lambda i, lay: np.exp(0.6 * np.sin(5 * W.cell_centres(lay, dom)).sum(axis=1)))
+    t = gpu_tree(w)
+    o = oracle_trees(w)[0]
+    lay = t.leaf_layout()[:, 1:]
+    assert np.array_equal(lay, o.leaf_layout())
+    eps = w.eps(0, lay)
+    phi = np.random.default_rng(5).standard_normal(t.n_leaf)
+    t.set_eps(eps)
+    o.set_eps(eps)
+    if homogeneous:
+        t.set_homogeneous_bc(True)
+        o2 = W.Domain(dom.dim, dom.base_cells, dom.lo, dom.hi, dom.bc_kind, [0.0] * 6)
+        o = oracle_trees(W.Workload("apply_op0", [o2], bs=16, max_refine=1, refine=refine,
+                                    variable_eps=True))[0]
+        o.set_eps(eps)
+    got = t.apply_operator(phi)
+    ref = o.apply(phi)
+    err = rel_err(got, ref)
+    print(f"homogeneous={homogeneous}: L phi rel err {err:.2e}", flush=True)
+    assert err <= 1e-13
+    # the tree's own phi and f are untouched: phi = 0, f = 0 still give a zero residual
+    assert np.all(t.get_phi() == 0.0)

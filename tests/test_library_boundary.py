@@ -96,6 +96,29 @@ def test_invalid_arguments_are_rejected():
     mg.Tree([mg.Domain(2, (32, 32), (0, 0), (1, 1), [1, 0, 2, 2])], bs=16, bind=False, params=axi)
 
 
+def test_singular_domains_are_rejected_unless_regularised():
+    # without a Dirichlet face the Poisson operator annihilates constants: a fully
+    # periodic domain is made consistent by the coarsest grid's mean removal, Neumann
+    # (and Neumann + periodic) domains are rejected; a Helmholtz term makes them regular
+    from paper_1901_11370_amd import mg
+    N, D, P = mg.MG_BC_NEUMANN, mg.MG_BC_DIRICHLET, mg.MG_BC_PERIODIC
+    for kinds in ([N] * 6, [P, P, N, N, N, N], [P, P, P, P, N, N], [N, N, P, P, P, P]):
+        d = mg.Domain(3, (32, 32, 32), (0, 0, 0), (1, 1, 1), kinds)
+        with pytest.raises(mg.MGError) as e:
+            mg.Tree([d], bs=16, bind=False)
+        assert e.value.status == mg.MG_ERR_ARG
+        mg.Tree([d], bs=16, bind=False, params=mg.default_params(helmholtz_lambda=1.0))
+    with pytest.raises(mg.MGError):
+        mg.Tree([mg.Domain(2, (32, 32), (0, 0), (1, 1), [N, N, P, P])], bs=16, bind=False)
+    # one singular member makes the whole forest invalid
+    ok = mg.Domain(3, (32, 32, 32), (0, 0, 0), (1, 1, 1), [D] * 6)
+    bad = mg.Domain(3, (32, 32, 32), (0, 0, 0), (1, 1, 1), [N] * 6)
+    with pytest.raises(mg.MGError):
+        mg.Tree([ok, bad], bs=16, bind=False)
+    for kinds in ([P] * 6, [D] + [N] * 5, [N, D, P, P, P, P]):
+        mg.Tree([mg.Domain(3, (32, 32, 32), (0, 0, 0), (1, 1, 1), kinds)], bs=16, bind=False)
+
+
 def test_degenerate_arguments_are_rejected_on_the_host():
     import ctypes
     from paper_1901_11370_amd import mg
@@ -130,3 +153,33 @@ def test_degenerate_arguments_are_rejected_on_the_host():
     assert L.mg_default_params(None) == mg.MG_ERR_ARG
     for st in range(-7, 1):
         assert L.mg_strerror(st)
+
+
+def test_boundary_face_list_on_a_refined_tree():
+    # mg_boundary_faces lists exactly the leaf-cell faces on physical Dirichlet faces,
+    # face direction by direction, leaf order within a direction (host code, no GPU)
+    from paper_1901_11370_amd import mg
+    w = W.x1("corner", base=32)
+    t = gpu_tree(w, bind=False)
+    cells, faces = t.boundary_faces()
+    lay = t.leaf_layout()
+    n_lev = 32 * 2 ** lay[:, 1]
+    want_c, want_f = [], []
+    for f in range(6):
+        a, side = f // 2, f % 2
+        on = lay[:, 2 + a] == (n_lev - 1 if side else 0)
+        want_c.append(np.flatnonzero(on))
+        want_f.append(np.full(on.sum(), f))
+    # within a direction the list is block-major; compare as sets per direction and
+    # check the block order (leaf order) separately
+    for f in range(6):
+        got = cells[faces == f]
+        assert np.array_equal(np.sort(got), want_c[f])
+        blocks = got // 4096
+        assert np.all(np.diff(blocks) >= 0)
+    assert len(cells) == sum(len(c) for c in want_c)
+    # Neumann and periodic faces are not listed
+    d = mg.Domain(3, (32, 32, 32), (0, 0, 0), (1, 1, 1), [0, 1, 2, 2, 1, 0])
+    t2 = mg.Tree([d], bs=16, bind=False)
+    c2, f2 = t2.boundary_faces()
+    assert set(f2.tolist()) == {0, 5} and len(c2) == 2 * 32 * 32
