@@ -78,9 +78,11 @@ def _oracle_adjoint(w, t, tgt, fl, el, rel_tol):
 
 
 def _check_against_oracle(sizes, tol):
-    # FP64 forward and adjoint on both sides, each solved to the rounding floor
+    # FP64 forward and adjoint on both sides: the GPU to 1e-11 (the FP64 floor of the
+    # adjoint problem at 128^3 and above, with its smaller right-hand side, lies near
+    # 1e-12), the reference to 1e-12
     w, t, f, e, tgt, fl, el = _setup(sizes, precision=0)
-    phi, gf, ge = _grads(t, f, e, tgt, rel_tol=1e-12, max_cycles=40)
+    phi, gf, ge = _grads(t, f, e, tgt, rel_tol=1e-11, max_cycles=40)
     ref = _oracle_adjoint(w, t, tgt, fl, el, 1e-12)
     gfs, ges = split(t, gf.cpu().numpy()), split(t, ge.cpu().numpy())
     phs = split(t, phi.cpu().numpy())
