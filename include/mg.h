@@ -219,6 +219,19 @@ int mg_fmg(mg_tree *t, int n_cycles);
 int mg_residual_norm(mg_tree *t, double *max_rel, double *l2_rel);
 int mg_domain_residual_norms(mg_tree *t, double *max_rel, double *l2_rel);
 
+/* For callers that cannot allocate or synchronise (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the composite residual of
+ * mg_residual_norm, asynchronous on the bound stream, with no allocation of any kind.
+ * d_norms (device memory, 4 x n_domains doubles) receives per domain max|r|,
+ * sum vol r^2, max|f|, sum vol f^2 (the relative norms are max|r|/max|f| and
+ * sqrt(sum vol r^2 / sum vol f^2)).  The per-block reduction partials live in a fixed
+ * device array of the library (one per GPU, 2 MiB, held until the process ends),
+ * which limits the tree to 65536 leaf blocks (MG_ERR_ARG beyond).  Every call on a GPU
+ * shares that array: calls that overlap on one GPU (several streams, threads or
+ * trees at once) race and must be ordered by the caller.  Same side effect as
+ * mg_residual_norm on refined trees (parents take the mean of their children). */
+int mg_residual_norms_static(mg_tree *t, double *d_norms);
+
 /* Solve to max-norm relative residual <= rel_tol: optional FMG first, then V-cycles
  * (FP64), or FP64 iterative refinement around FP32 cycles (MG_MIXED), checking the
  * norm after every cycle / refinement step.  With MG_MIXED and params.krylov = m > 0

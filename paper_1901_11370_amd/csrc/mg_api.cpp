@@ -912,6 +912,12 @@ int mg_tree_bind(mg_tree *t, void *device_store, size_t bytes, void *hip_stream)
         prepare_kernels();
         HIP_OR_FAIL(t, hipStreamCreateWithFlags(&t->cap, hipStreamNonBlocking));
     }
+    {
+        // device address of the fixed reduction scratch on this device (set-up of
+        // mg_residual_norms_static)
+        double *p = nullptr;
+        if (static_partials(&p)) return fail(t, MG_ERR_DEVICE, "hipGetSymbolAddress of the reduction scratch failed");
+    }
     if (!t->h_norms) {
         HIP_OR_FAIL(t, hipHostMalloc((void **)&t->h_norms, 4 * (size_t)t->T.ndom * 8, hipHostMallocDefault));
         HIP_OR_FAIL(t, hipHostGetDevicePointer((void **)&t->d_hnorms, t->h_norms, 0));
@@ -1230,6 +1236,26 @@ int mg_domain_residual_norms(mg_tree *t, double *max_rel, double *l2_rel) {
     if ((rc = read_norms(t, &n))) return rc;
     rel_norms(t, n, max_rel, l2_rel);
     return MG_OK;
+}
+
+int mg_residual_norms_static(mg_tree *t, double *d_norms) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!d_norms) return MG_ERR_ARG;
+    if (t->nleafblk > static_partial_blocks())
+        return fail(t, MG_ERR_ARG, "%lld leaf blocks exceed the %d of the fixed reduction scratch",
+                    (long long)t->nleafblk, static_partial_blocks());
+    double *part = nullptr;
+    if (static_partials(&part)) return fail(t, MG_ERR_DEVICE, "hipGetSymbolAddress of the reduction scratch failed");
+    // the kernels of mg_residual_norm; every partial is written before it is read
+    Driver<double> D = d64(t);
+    if (t->T.refined) D.sync();
+    D.L.partials = part;
+    D.L.dom_norms = d_norms;
+    D.L.host_norms = nullptr;
+    launch_norm64(D.L, t->P64, (int)t->nleafblk, var(t), nullptr, nullptr);
+    launch_reduce_norms(D.L);
+    return check_launch(t);
 }
 
 int mg_residual_norm(mg_tree *t, double *max_rel, double *l2_rel) {

@@ -140,6 +140,10 @@ enum { TAIL_VCYCLE = 0, TAIL_FMG = 1 };
 void prepare_kernels();
 // LDS bytes the single-workgroup coarse solver has for a domain's grids.
 int tail_lds_bytes();
+// Device address, on the current device, of the fixed per-block reduction partials
+// (looked up on first use per device); 0 on success.  Capacity in leaf blocks.
+int static_partials(double **out);
+int static_partial_blocks();
 
 // FP64 composite residual over the leaf blocks; optionally writes r (cast) into rout.
 void launch_norm64(const Launch &L, const Plane<double> &P, int nleafblk, bool var, float *rout32,

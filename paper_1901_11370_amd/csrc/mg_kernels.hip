@@ -12,6 +12,8 @@
 #include <cmath>
 #include <cstdio>
 
+#include <mutex>
+
 #include "mg_internal.hpp"
 
 namespace mgx {
@@ -2596,6 +2598,36 @@ template <typename K>
 static void allow_lds(K kernel) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, kTailLds);
 }
+
+// ------------------------------------------------ fixed reduction scratch
+// Per-block partials of the allocation-free residual norm live in this file-scope
+// device array: one copy per GPU, held until the process ends.  Its name is a
+// host-side stand-in in host code, so it is never passed to a kernel; the device
+// address of each GPU's copy is looked up once per device (hipGetSymbolAddress, with
+// that device current) and that address is used instead.
+constexpr int kStaticPartialBlocks = 1 << 16;   // leaf blocks, 4 doubles each: 2 MiB
+static __device__ __align__(256) double scratch[4 * kStaticPartialBlocks];
+
+namespace {
+constexpr int kMaxDevices = 64;
+double *g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+}  // namespace
+
+int static_partials(double **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return -1;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -1;
+        g_scratch[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch[dev];
+    return 0;
+}
+
+int static_partial_blocks() { return kStaticPartialBlocks; }
 
 void prepare_kernels() {
     allow_lds(k_tail<double, 3, true, true>);

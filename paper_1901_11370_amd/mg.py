@@ -81,6 +81,7 @@ _SIGS = {
     "mg_vcycle": ([_vp, ctypes.c_int], ctypes.c_int),
     "mg_fmg": ([_vp, ctypes.c_int], ctypes.c_int),
     "mg_residual_norm": ([_vp, _P(_d), _P(_d)], ctypes.c_int),
+    "mg_residual_norms_static": ([_vp, _vp], ctypes.c_int),
     "mg_domain_residual_norms": ([_vp, _P(_d), _P(_d)], ctypes.c_int),
     "mg_solve": ([_vp, _d, ctypes.c_int, ctypes.c_int, _P(ctypes.c_int)], ctypes.c_int),
     "mg_solve_stats": ([_vp, ctypes.c_int, _P(_d), _P(_d), _P(ctypes.c_int)], ctypes.c_int),
