@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -37,6 +39,7 @@ def _args():
     p.add_argument("--tol", type=float, default=1e-10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-mixed", action="store_true")
+    p.add_argument("--no-extra", action="store_true", help="skip the AMR and differentiable-solve legs")
     p.add_argument("--cpu-sample-cycles", type=int, default=1, help="V-cycles after the FMG in the CPU sample")
     p.add_argument("--workload", default="periodic256",
                    choices=["periodic256", "dirichlet2d", "amr-literal", "amr-nested", "varcoef-nested", "batch",
@@ -104,6 +107,10 @@ def run_solve(tree, f_dev, zero_dev, tol):
 
 
 def timed(tree, f_dev, zero_dev, tol, steps, warmup, profile=False, fn=None):
+    """W untimed steps, then exactly `steps` steps between two synchronisations; each
+    step is also bracketed by HIP events on the tree's stream.  Returns (mean seconds
+    per step over the region, cycles, return codes, profile record or None, per-step
+    event seconds)."""
     import torch
     fn = fn or (lambda: run_solve(tree, f_dev, zero_dev, tol))
     for _ in range(warmup):
@@ -111,37 +118,89 @@ def timed(tree, f_dev, zero_dev, tol, steps, warmup, profile=False, fn=None):
     torch.cuda.synchronize()
     if profile:
         tree.profile_enable(True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    stream = getattr(tree, "stream", None) or torch.cuda.current_stream()
     t0 = time.perf_counter()
     cyc = []
     rcs = []
-    for _ in range(steps):
+    for e0, e1 in evs:
+        e0.record(stream)
         c, rc = fn()
+        e1.record(stream)
         cyc.append(c)
         rcs.append(rc)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    per = [e0.elapsed_time(e1) * 1e-3 for e0, e1 in evs]
     prof = tree.profile_read() if profile else None
     if profile:
         tree.profile_enable(False)
-    return dt, cyc, rcs, prof
+    return dt, cyc, rcs, prof, per
 
 
-def cpu_baseline(w, sample_cycles):
+def _median(x):
+    x = sorted(x)
+    n = len(x)
+    return x[n // 2] if n % 2 else 0.5 * (x[n // 2 - 1] + x[n // 2])
+
+
+def cpu_info():
+    """Host CPU model and the threads the reference solver's OpenMP loops use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(w, sample_cycles, small_n=128, tol=1e-10):
     """The reference solver, as it stands, on the host: one FMG cycle plus
-    `sample_cycles` V-cycles of the same workload, single thread."""
+    `sample_cycles` V-cycles of the benchmark workload (one thread and all threads of
+    its OpenMP block loops), and the time to `tol` of the same problem at small_n^3."""
+    import oracle
     from oracle import OracleTree
+    from paper_1901_11370_amd import workloads as W
     d = w.domains[0]
+    model, ncpu = cpu_info()
+    nthreads = oracle.set_threads(0)          # the OpenMP default (OMP_NUM_THREADS)
+    out = {"unit": "cell-updates/s", "kind": "oracle", "cpu_model": model, "nproc": ncpu}
     o = OracleTree(d.dim, d.base_cells, d.lo, d.hi, d.bc_kind, bs=w.bs)
-    lay = o.leaf_layout()
-    o.set_rhs(w.rhs(0, lay))
-    t0 = time.perf_counter()
-    o.fmg()
-    o.vcycle(sample_cycles)
-    dt = time.perf_counter() - t0
-    cycles = 1 + sample_cycles
-    return {"value": o.n_leaf * cycles / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"FMG + {sample_cycles} V-cycle(s) of the same {d.base_cells[0]}^3 problem "
-                      f"({o.n_leaf} leaf cells), {dt:.2f} s on one host thread"}
+    f = w.rhs(0, o.leaf_layout())
+    legs = {}
+    for nt in (nthreads, 1):
+        oracle.set_threads(nt)
+        o.set_rhs(f)
+        o.set_phi(np.zeros(o.n_leaf))
+        t0 = time.perf_counter()
+        o.fmg()
+        o.vcycle(sample_cycles)
+        dt = time.perf_counter() - t0
+        legs[nt] = o.n_leaf * (1 + sample_cycles) / dt
+    small = W.config2(n=small_n)
+    ds = small.domains[0]
+    os_ = OracleTree(ds.dim, ds.base_cells, ds.lo, ds.hi, ds.bc_kind, bs=small.bs)
+    fs = small.rhs(0, os_.leaf_layout())
+    tt = {}
+    for nt in (nthreads, 1):
+        oracle.set_threads(nt)
+        os_.set_rhs(fs)
+        os_.set_phi(np.zeros(os_.n_leaf))
+        t0 = time.perf_counter()
+        hist = os_.solve(rel_tol=tol, max_cycles=40, fmg_first=True)
+        tt[nt] = (time.perf_counter() - t0, len(hist), hist[-1])
+    oracle.set_threads(nthreads)
+    out.update({"value": legs[nthreads], "cores": nthreads, "value_1_thread": legs[1],
+                "sample": f"FMG + {sample_cycles} V-cycle(s) of the same {d.base_cells[0]}^3 problem "
+                          f"({o.n_leaf} leaf cells), OpenMP over the blocks of a level",
+                "time_to_tol_s": {f"{small_n}^3_{nthreads}_threads": tt[nthreads][0],
+                                  f"{small_n}^3_1_thread": tt[1][0]},
+                "time_to_tol_cycles": tt[1][1], "time_to_tol_final_rel_residual": tt[1][2]})
+    return out
 
 
 def _tree_of(w, precision, mg, krylov=0, helmholtz_lambda=0.0):
@@ -184,7 +243,7 @@ def report(a):
             t.vcycle(10)
             r, _ = t.residual_norm()
             return 10, 0
-        dt, _, _, _ = timed(t, f, z, a.tol, a.steps, a.warmup, fn=ten)
+        dt, _, _, _, _ = timed(t, f, z, a.tol, a.steps, a.warmup, fn=ten)
         out = dict(base, metric="time per 10 V(2,2) cycles", value=t.n_leaf * 10 / dt, ms_per_step=dt * 1e3,
                    dtype="f64", config={"workload": "poisson2d_128^2_dirichlet_sine_10xV(2,2)", "leaf_cells": t.n_leaf},
                    final_rel_residual=t.residual_norm()[0])
@@ -214,7 +273,7 @@ def report(a):
             if e is not None:
                 t.set_eps(e)
             z = torch.zeros_like(f)
-            dt, cyc, rcs, _ = timed(t, f, z, a.tol, a.steps, a.warmup)
+            dt, cyc, rcs, _, _ = timed(t, f, z, a.tol, a.steps, a.warmup)
             r, s_ = t.solve_stats()
             out[key] = {"time_to_tol_ms": dt * 1e3, "cycles": cyc[-1], "converged": rcs[-1] == 0,
                         "final_rel_residual": float(r[-1]), "value": t.n_leaf * cyc[-1] / dt,
@@ -343,7 +402,7 @@ def report(a):
                     t.divb_project(B, e)
                     return c, rc
 
-                dt, cyc, rcs, _ = timed(t, None, None, a.tol, a.steps, a.warmup, fn=clean)
+                dt, cyc, rcs, _, _ = timed(t, None, None, a.tol, a.steps, a.warmup, fn=clean)
 
                 def part(fn):
                     torch.cuda.synchronize()
@@ -388,7 +447,7 @@ def report(a):
                     t.freespace_bc(k)
                     return t.solve(rel_tol=a.tol, max_cycles=MAX_CYCLES, fmg_first=True, raise_on_fail=False)
 
-                dt, cyc, rcs, _ = timed(t, None, None, a.tol, a.steps, a.warmup, fn=run)
+                dt, cyc, rcs, _, _ = timed(t, None, None, a.tol, a.steps, a.warmup, fn=run)
                 for _ in range(a.warmup):
                     bc()
                 torch.cuda.synchronize()
@@ -519,13 +578,114 @@ def report(a):
         torch.cuda.synchronize()
         t_fwd = time.perf_counter() - t0
         fwd_res = [float(x) for x in t.domain_residual_norms()[0]]
-        dt, _, _, _ = timed(t, f, None, a.tol, a.steps, a.warmup, fn=fwd_bwd)
+        dt, _, _, _, _ = timed(t, f, None, a.tol, a.steps, a.warmup, fn=fwd_bwd)
         out = dict(base, metric="forward + adjoint backward time", value=t.n_leaf / dt, ms_per_step=dt * 1e3,
                    dtype="f32 cycles in f64 refinement",
                    config={"workload": w.name, "leaf_cells": t.n_leaf, "domains": len(w.domains)},
                    forward_ir_steps=cyc, forward_ms=t_fwd * 1e3, forward_domain_residuals=fwd_res)
         print(json.dumps(out), flush=True)
         return
+
+
+def roofline_of(prof, kernel, dtp):
+    """Roofline record of the event-timed finest-level smoothing launches."""
+    launches, total_ms, bytes_per = prof
+    if not launches:
+        return None
+    avg_ms = total_ms / launches
+    achieved = bytes_per / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "kernel": kernel, "avg_us": avg_ms * 1e3, "launches": launches,
+            "algorithmic_bytes_per_launch": bytes_per, "events_region_ms_per_step": dtp * 1e3}
+
+
+def amr_leg(a, mg, W):
+    """The AMR workload at its ~1e8-leaf-cell layout (base 128^3, three refinement levels
+    nested around the centre, four Gaussian sources, phi = 0 on the boundary): FP64 and
+    mixed time to tolerance, with the event-timed finest-level smoothing kernel."""
+    import torch
+    w = W.config3(nested=True)
+    steps = max(1, min(a.steps, 8))
+    out = {"workload": "amr3d_base128_3levels_nested_4gauss_dirichlet_fmg+V(2,2)_to_1e-10"}
+    for prec, key in ((mg.MG_FP64, "fp64"), (mg.MG_MIXED, "mixed")):
+        t = _tree_of(w, prec, mg)
+        f, _, _ = _inputs(w, t)
+        z = torch.zeros_like(f)
+        dt, cyc, rcs, _, per = timed(t, f, z, a.tol, steps, 2)
+        r, _ = t.solve_stats()
+        dtp, _, _, prof, _ = timed(t, f, z, a.tol, 2, 1, profile=True)
+        leg = {"time_to_tol_ms": dt * 1e3, "time_to_tol_ms_median_events": _median(per) * 1e3,
+               "cycles": cyc[-1], "converged": all(rc == 0 for rc in rcs), "final_rel_residual": float(r[-1]),
+               "leaf_cell_cycles_per_s": t.n_leaf * cyc[-1] / dt, "leaf_cells": t.n_leaf,
+               "roofline": roofline_of(prof, f"k_gsrb<{'double' if prec == 0 else 'float'},3,16> finest AMR level "
+                                             "(one colour)", dtp)}
+        if key == "fp64":
+            phi64 = t.get_phi()
+        else:
+            leg["rel_diff_vs_fp64_solution"] = float(np.abs(t.get_phi() - phi64).max() / np.abs(phi64).max())
+        out[key] = leg
+        del t, f, z
+        torch.cuda.empty_cache()
+    return out
+
+
+def batch_leg(a, mg, W):
+    """The differentiable solve: forward (FP32 cycles in FP64 refinement to the
+    tolerance) and adjoint backward of the six-member batch (64^3 ... 256^3, log-normal
+    eps), with the event-timed finest-level variable-coefficient FP32 sweep."""
+    import torch
+    from paper_1901_11370_amd.autograd import mg_solve
+    w = W.config5()
+    t = _tree_of(w, mg.MG_MIXED, mg)
+    f, e, lay = _inputs(w, t)
+    tgt = torch.from_numpy(np.concatenate([w.target(i, lay[lay[:, 0] == i][:, 1:])
+                                           for i in range(len(w.domains))])).cuda()
+
+    def fwd_bwd():
+        ff = f.clone().requires_grad_(True)
+        ee = e.clone().requires_grad_(True)
+        phi = mg_solve(ff, ee, t, a.tol, a.max_cycles)
+        J = 0.5 * torch.sum((phi - tgt) ** 2)
+        J.backward()
+        return 1, 0
+    steps = max(1, min(a.steps, 8))
+    dt, _, _, _, per = timed(t, f, None, a.tol, steps, 2, fn=fwd_bwd)
+    t.set_eps(e)
+
+    def fwd():
+        t.set_rhs(f)
+        t.set_phi(torch.zeros_like(f))
+        return t.solve(rel_tol=a.tol, max_cycles=a.max_cycles, raise_on_fail=False)
+    dtf, cyc, rcs, _, _ = timed(t, f, None, a.tol, steps, 1, fn=fwd)
+    dtp, _, _, prof, _ = timed(t, f, None, a.tol, 2, 1, profile=True, fn=fwd)
+    out = {"workload": "diffsolve3d_batch6 (64^3..256^3, log-normal eps), J = 1/2 |phi - phi_t|^2",
+           "leaf_cells": t.n_leaf, "fwd_bwd_ms": dt * 1e3, "fwd_bwd_ms_median_events": _median(per) * 1e3,
+           "forward_ms": dtf * 1e3, "forward_ir_steps": cyc[-1], "forward_converged": all(rc == 0 for rc in rcs),
+           "roofline": roofline_of(prof, "k_gsrb<float,3,16,var-eps> finest level (one colour)", dtp)}
+    del t
+    torch.cuda.empty_cache()
+    return out
+
+
+def copy_bandwidth(mib=1024):
+    """Event-timed device-to-device copy of `mib` MiB: the practical streaming rate."""
+    import torch
+    n = mib * 1024 * 1024 // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def main():
@@ -542,7 +702,6 @@ def main():
     if a.workload != "periodic256":
         report(a)
         return
-    import numpy as np
     import torch
     from paper_1901_11370_amd import mg
     from paper_1901_11370_amd import workloads as W
@@ -559,11 +718,11 @@ def main():
     n_leaf = t64.n_leaf
 
     # headline timed region: cycle sequences replayed from captured graphs
-    dt, cyc, rcs, _ = timed(t64, f_dev, zero_dev, a.tol, a.steps, a.warmup)
+    dt, cyc, rcs, _, per = timed(t64, f_dev, zero_dev, a.tol, a.steps, a.warmup)
     res, secs = t64.solve_stats()
     # roofline: HIP events around every finest-level smoothing launch over a second
     # timed region of the same solves (events need the kernels launched one by one)
-    dtp, _, _, prof = timed(t64, f_dev, zero_dev, a.tol, a.steps, 1, profile=True)
+    dtp, _, _, prof, _ = timed(t64, f_dev, zero_dev, a.tol, a.steps, 1, profile=True)
     cycles = cyc[-1]
     # smoothing updates per cycle: every level's cells, (n_down + n_up) sweeps
     gs_updates = float(ncell.sum()) * 4 * cycles
@@ -578,37 +737,41 @@ def main():
         "config": {"workload": f"poisson3d_{a.n}^3_periodic_32gauss_fmg+V(2,2)_to_{a.tol:g}",
                    "leaf_cells": n_leaf, "block": "16^3", "levels": int(len(nb))},
         "time_to_tol_ms": dt * 1e3,
+        "time_to_tol_ms_median_events": _median(per) * 1e3,
         "cycles_to_tol": cycles,
         "converged": all(rc == 0 for rc in rcs),
         "final_rel_residual": float(res[-1]),
         "gs_point_updates_per_s": gs_updates / dt,
     }
-    launches, total_ms, bytes_per = prof
-    if launches:
-        avg_ms = total_ms / launches
-        achieved = bytes_per / (avg_ms * 1e-3) / 1e9
-        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(int(ncell[-1])),
-                           "kernel": "k_gsrb<double,3,16> finest level (one colour)",
-                           "avg_us": avg_ms * 1e3, "launches": launches,
-                           "algorithmic_bytes_per_launch": bytes_per,
-                           "events_region_ms_per_step": dtp * 1e3}
+    roof = roofline_of(prof, "k_gsrb<double,3,16> finest level (one colour)", dtp)
+    if roof:
+        roof["traffic"] = traffic_from_profile(int(ncell[-1]))
+        roof["copy_gbs_in_run"] = copy_bandwidth()
+        roof["frac_of_copy"] = roof["achieved"] / roof["copy_gbs_in_run"]
+        out["roofline"] = roof
 
     if not a.no_mixed:
         tmx = mg.Tree([dom], bs=16, params=mg.default_params(precision=mg.MG_MIXED))
-        dtm, cycm, rcsm, _ = timed(tmx, f_dev, zero_dev, a.tol, a.steps, a.warmup)
+        dtm, cycm, rcsm, _, perm = timed(tmx, f_dev, zero_dev, a.tol, a.steps, a.warmup)
         resm, _ = tmx.solve_stats()
+        dtmp, _, _, profm, _ = timed(tmx, f_dev, zero_dev, a.tol, 2, 1, profile=True)
         phi64 = t64.get_phi()
         phim = tmx.get_phi()
         p64 = phi64 - phi64.mean()
         pm = phim - phim.mean()
-        out["mixed"] = {"time_to_tol_ms": dtm * 1e3, "ir_steps": cycm[-1],
-                        "converged": all(rc == 0 for rc in rcsm),
+        out["mixed"] = {"time_to_tol_ms": dtm * 1e3, "time_to_tol_ms_median_events": _median(perm) * 1e3,
+                        "ir_steps": cycm[-1], "converged": all(rc == 0 for rc in rcsm),
                         "final_rel_residual": float(resm[-1]),
                         "value": n_leaf * cycm[-1] / dtm, "unit": "cell-updates/s",
                         "speedup_vs_fp64": dt / dtm,
-                        "rel_diff_vs_fp64_solution": float(np.abs(pm - p64).max() / np.abs(p64).max())}
+                        "rel_diff_vs_fp64_solution": float(np.abs(pm - p64).max() / np.abs(p64).max()),
+                        "roofline": roofline_of(profm, "k_gsrb<float,3,16> finest level (one colour)", dtmp)}
         del tmx
+    del t64
+    torch.cuda.empty_cache()
+    if not a.no_extra:
+        out["amr_nested"] = amr_leg(a, mg, W)
+        out["diffsolve_batch"] = batch_leg(a, mg, W)
 
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_sample_cycles)

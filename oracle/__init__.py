@@ -26,7 +26,7 @@ REFINE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes
 def build(force: bool = True) -> str:
     """Compile the oracle into ``libmg_oracle.so`` next to its source."""
     if force or not os.path.exists(_LIB_PATH):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-Wall", "-o",
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o",
                _LIB_PATH + ".tmp", _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
@@ -81,11 +81,18 @@ def lib():
         L.og_last_coarse_exit.restype = ctypes.c_int
         L.og_set_coarse_stall.argtypes = [vp, ctypes.c_int]
         L.og_coarse_solve.argtypes = [vp]
+        L.og_set_threads.argtypes = [ctypes.c_int]
+        L.og_set_threads.restype = ctypes.c_int
         L.og_boundary_faces.argtypes = [vp, P(d), P(i32)]
         L.og_boundary_faces.restype = i64
         L.og_set_boundary_values.argtypes = [vp, P(d)]
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads of the reference solver's block loops (results do not depend on it)."""
+    return int(lib().og_set_threads(int(n)))
 
 
 def _dp(a):

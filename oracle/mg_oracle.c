@@ -4,6 +4,9 @@
  * TEST INFRASTRUCTURE ONLY (see mg_oracle.h).  Plain, slow and written to be checked
  * against the paper by eye: every routine names the passage it follows.  It is built
  * with -O2 -ffp-contract=off so that no fused multiply-add changes its rounding.
+ * With OpenMP the loops over the blocks of one level run in parallel; each block writes
+ * only its own cells (and ghosts), and cells of one colour do not read each other, so
+ * the results do not depend on the thread count.  Sums over cells stay serial.
  *
  * Data layout: every block of every level stores each field as a (bs+2)^d array with
  * one layer of face ghost cells (Sec. 2.6: a single ghost layer, no diagonal ghosts).
@@ -14,6 +17,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OG_MAXLEV 40
 #define STALL 0.999     /* coarsest solve: progress means a residual below STALL x the lowest so far */
@@ -450,6 +456,7 @@ static void gather_leaf(const og_tree *t, int field, double *dst) {
 static void fill_ghosts_field(og_tree *t, int l, int field, int homogeneous) {
     const OLevel *L = &t->lev[l];
     int bs = L->bs;
+    #pragma omp parallel for schedule(static)
     for (int q = 0; q < L->n; q++) {
         OBlock *B = &t->blk[L->list[q]];
         double *u = B->fld[field];
@@ -670,6 +677,7 @@ static double gs_value(const og_tree *t, int l, const OBlock *B, int i, int j, i
  * the residual field meanwhile); then ghosts are refreshed. */
 static void jacobi_step(og_tree *t, int l) {
     const OLevel *L = &t->lev[l];
+    #pragma omp parallel for schedule(static)
     for (int q = 0; q < L->n; q++) {
         OBlock *B = &t->blk[L->list[q]];
         FOR_CELLS(t, l, i, j, k) {
@@ -678,6 +686,7 @@ static void jacobi_step(og_tree *t, int l) {
             B->fld[F_R][p] = v + t->omega * (gs_value(t, l, B, i, j, k) - v);
         }
     }
+    #pragma omp parallel for schedule(static)
     for (int q = 0; q < L->n; q++) {
         OBlock *B = &t->blk[L->list[q]];
         FOR_CELLS(t, l, i, j, k) {
@@ -695,6 +704,7 @@ static void smooth_step(og_tree *t, int l) {
         return;
     }
     for (int colour = 0; colour < 2; colour++) {
+        #pragma omp parallel for schedule(static)
         for (int q = 0; q < L->n; q++) {
             OBlock *B = &t->blk[L->list[q]];
             FOR_CELLS(t, l, i, j, k) {
@@ -709,6 +719,7 @@ static void smooth_step(og_tree *t, int l) {
 /* r = f - L v on every block of level l (Sec. 2.4). */
 static void residual_level(og_tree *t, int l) {
     const OLevel *L = &t->lev[l];
+    #pragma omp parallel for schedule(static)
     for (int q = 0; q < L->n; q++) {
         OBlock *B = &t->blk[L->list[q]];
         FOR_CELLS(t, l, i, j, k) {
@@ -724,6 +735,7 @@ static void residual_level(og_tree *t, int l) {
 static void restrict_field(og_tree *t, int l, int src, int dst) {
     const OLevel *C = &t->lev[l - 1];
     int nsub = 1 << t->dim;
+    #pragma omp parallel for schedule(static)
     for (int q = 0; q < C->n; q++) {
         OBlock *P = &t->blk[C->list[q]];
         if (!P->has_children) continue;
@@ -751,6 +763,7 @@ static void restrict_fas(og_tree *t, int l) {
     restrict_field(t, l, F_R, F_R);
     og_fill_ghosts_level(t, l - 1);
     const OLevel *C = &t->lev[l - 1];
+    #pragma omp parallel for schedule(static)
     for (int q = 0; q < C->n; q++) {
         OBlock *P = &t->blk[C->list[q]];
         if (!P->has_children) continue;
@@ -768,6 +781,7 @@ static void restrict_fas(og_tree *t, int l) {
  * Then the ghosts of level h. */
 static void correct_level(og_tree *t, int l) {
     const OLevel *L = &t->lev[l];
+    #pragma omp parallel for schedule(static)
     for (int q = 0; q < L->n; q++) {
         OBlock *B = &t->blk[L->list[q]];
         const OBlock *P = &t->blk[B->parent];
@@ -1042,4 +1056,15 @@ void og_block_field(const og_tree *t, int l, int ib, int field, double *out) {
 void og_set_block_field(og_tree *t, int l, int ib, int field, const double *in) {
     OBlock *B = &t->blk[t->lev[l].list[ib]];
     memcpy(B->fld[field], in, (size_t)npad(t, l) * sizeof(double));
+}
+
+/* Threads of the block loops (OpenMP builds; 1 otherwise). */
+int og_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

@@ -83,6 +83,9 @@ int og_last_coarse_exit(const og_tree *t);
 /* Length of the coarsest solve's stall window (default 8 steps); 0 removes it, which
  * leaves the paper's rule alone (tolerance or n_max). */
 void og_set_coarse_stall(og_tree *t, int steps);
+/* Threads for the loops over the blocks of a level (OpenMP builds); returns the count
+ * in use.  Results are identical for every thread count. */
+int og_set_threads(int n);
 /* The coarsest-grid solve alone, on the current v and f of level 0. */
 void og_coarse_solve(og_tree *t);
 

