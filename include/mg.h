@@ -88,7 +88,11 @@ typedef struct {
     int32_t precision;        /* MG_FP64, or MG_MIXED: FP32 cycles in FP64 refinement */
     int32_t variable_eps;     /* 0: eps = 1, constant-coefficient stencil; 1: eps field */
     int32_t ir_first_fmg;     /* mixed: the first refinement step runs an FP32 FMG cycle */
-    int32_t ir_vcycles;       /* mixed: FP32 V-cycles per refinement step (>= 1) */
+    int32_t ir_vcycles;       /* mixed: FP32 V-cycles per plain refinement step (>= 1;
+                                 default 3: with a contraction of ~0.1 per cycle three
+                                 cycles stay above the FP32 accuracy of the correction, and
+                                 each step costs one FP64 residual and one host check).
+                                 The FGMRES preconditioner is always one V-cycle. */
     int32_t graphs;           /* 1 (default): each cycle sequence (V-cycle, FMG cycle,
                                  refinement step, residual norm) is captured once as a
                                  HIP graph and replayed; 0: kernels launched one by one */

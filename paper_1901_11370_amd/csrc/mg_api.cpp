@@ -680,8 +680,8 @@ void enq_apply(mg_tree *t, double *z, double *w) {
     launch_norm64(D.L, Q, (int)t->nleafblk, var(t), nullptr, w);
 }
 
-// z = M^-1 v: FP32 cycles (ir_vcycles V-cycles from zero, homogeneous boundary values)
-// on the correction equation with right-hand side v.
+// z = M^-1 v: one FP32 V-cycle from zero (homogeneous boundary values) on the
+// correction equation with right-hand side v.
 void enq_precond(mg_tree *t, double *v, double *z) {
     Driver<float> D = d32(t);
     const Plane<float> &P = t->P32;
@@ -689,7 +689,7 @@ void enq_precond(mg_tree *t, double *v, double *z) {
     K<float>::zero(D.L, P.v, (size_t)(t->nb * t->nc));
     K<float>::zero(D.L, P.vg, (size_t)(t->nb * t->ng));
     K<float>::zero(D.L, P.tv, (size_t)t->T.tail_cells);
-    for (int c = 0; c < std::max(1, t->prm.ir_vcycles); c++) D.vcycle(t->T.nlev - 1, all_mask(t));
+    D.vcycle(t->T.nlev - 1, all_mask(t));
     launch_vec_blocks<float>(D.L, P.v, z, (int)t->nleafblk, false);
 }
 
@@ -822,7 +822,7 @@ int mg_default_params(mg_params *p) {
     p->precision = MG_FP64;
     p->variable_eps = 0;
     p->ir_first_fmg = 1;
-    p->ir_vcycles = 1;
+    p->ir_vcycles = 3;
     p->graphs = 1;
     p->krylov = 0;
     p->smoother = MG_SMOOTH_GSRB;

@@ -1356,6 +1356,14 @@ struct Tail {
         const TailLev g = lv[0];
         bool per = g.lam == 0.0;   // the regular Helmholtz operator needs no mean removal
         for (int f = 0; f < 2 * D; f++) per = per && bc.kind[f] == MG_BC_PERIODIC;
+        if (per && g.ncell == 1) {
+            // one cell, periodic on every axis: the operator is zero, the mean removal
+            // leaves f = 0 and so a zero residual, and the rule stops after its one step,
+            // which leaves v unchanged (its value is the free constant of the problem)
+            if (threadIdx.x == 0) tf[tix<D>(g, 0, 0, 0)] = T(0);
+            __syncthreads();
+            return 1;
+        }
         if (per) {
             double s = 0.0;
             for (int c = threadIdx.x; c < g.ncell; c += NT) {
@@ -1523,8 +1531,6 @@ __global__ void __launch_bounds__((tail_threads<VAR, D>())) k_tail(Plane<T> P, D
     const int top = tb.tail_top[dm];
     int64_t first;
     const int n = (int)tail_span(tb, dm, top, D, &first);
-    tail_setup(tb, dm, top + 1, D, first, lvs, &bcs);
-    if (threadIdx.x == 0) nops = tail_ops(ops, mode, top);
     // LDS holds v and f of every grid, v_old below the top grid (v_old of the top grid
     // is written to global memory, where the block level above reads it) and eps.  The
     // cycle reads only v and f of the top grid (and eps) from outside and leaves only v
@@ -1539,27 +1545,29 @@ __global__ void __launch_bounds__((tail_threads<VAR, D>())) k_tail(Plane<T> P, D
         }
         T *sv = reinterpret_cast<T *>(smem);
         T *sf = sv + n, *so = sf + n, *se = so + nold;
-        __syncthreads();
-        const TailLev &g = lvs[top];
-        // all loads of a batch are issued before the first LDS store, so the copy
-        // costs one memory round trip per batch rather than one per element
+        // The top grid (padded) is the last one: offset nold, n - nold cells.  Its copy
+        // needs no set-up data, so its loads and the set-up's table loads are in flight
+        // together; all loads of a batch come before its first LDS store.
+        const int toff = nold, tnp = n - nold;
         constexpr int CB = 8;
-        for (int q0 = 0; q0 < g.npad; q0 += CB * NT) {
+        tail_setup(tb, dm, top + 1, D, first, lvs, &bcs);
+        if (threadIdx.x == 0) nops = tail_ops(ops, mode, top);
+        for (int q0 = 0; q0 < tnp; q0 += CB * NT) {
             T a[CB], c[CB];
 #pragma unroll
             for (int r = 0; r < CB; r++) {
                 const int q = q0 + threadIdx.x + r * NT;
-                if (q < g.npad) {
-                    a[r] = P.tv[first + g.off + q];
-                    c[r] = P.tf[first + g.off + q];
+                if (q < tnp) {
+                    a[r] = P.tv[first + toff + q];
+                    c[r] = P.tf[first + toff + q];
                 }
             }
 #pragma unroll
             for (int r = 0; r < CB; r++) {
                 const int q = q0 + threadIdx.x + r * NT;
-                if (q < g.npad) {
-                    sv[g.off + q] = a[r];
-                    sf[g.off + q] = c[r];
+                if (q < tnp) {
+                    sv[toff + q] = a[r];
+                    sf[toff + q] = c[r];
                 }
             }
         }
@@ -1581,8 +1589,10 @@ __global__ void __launch_bounds__((tail_threads<VAR, D>())) k_tail(Plane<T> P, D
         const Tail<T, D, VAR> tl{lvs, bcs, red, sv, so, sf, VAR ? se : nullptr, P.tvold + first, top,
                                  P.tv2 ? P.tv2 + first : nullptr, tp.jacobi, tp.omega};
         steps = tl.run(ops, __builtin_amdgcn_readfirstlane(nops), tp);
-        for (int q = threadIdx.x; q < g.npad; q += NT) P.tv[first + g.off + q] = sv[g.off + q];
+        for (int q = threadIdx.x; q < tnp; q += NT) P.tv[first + toff + q] = sv[toff + q];
     } else {
+        tail_setup(tb, dm, top + 1, D, first, lvs, &bcs);
+        if (threadIdx.x == 0) nops = tail_ops(ops, mode, top);
         __syncthreads();
         const Tail<T, D, VAR> tl{lvs, bcs, red, P.tv + first, P.tvold + first, P.tf + first,
                                  VAR ? P.teps + first : nullptr, nullptr, top,

@@ -413,7 +413,7 @@ def test_mixed_iterates_follow_fp64_cycles(case):
         w = W.config5(sizes=(32, 64))
     else:
         w = W.config3(nested=False, base=32)
-    t = gpu_tree(w, precision=1)
+    t = gpu_tree(w, precision=1, ir_vcycles=1)   # one FP32 V-cycle per refinement step
     refs = oracle_trees(w)
     f, e = inputs(w, t)
     if w.variable_eps:
