@@ -153,6 +153,37 @@ struct Stager {
     }
 };
 
+// A thread's run of N consecutive values, moved with the widest aligned vectors (the
+// run starts at a multiple of N values, and every array starts 256-byte aligned).
+template <typename T, int N>
+__device__ __forceinline__ void ld_run(const T *__restrict__ src, T (&dst)[N]) {
+    constexpr int B = N * (int)sizeof(T);
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int c = 0; c < B / 16; c++) reinterpret_cast<uint4 *>(dst)[c] = reinterpret_cast<const uint4 *>(src)[c];
+    } else if constexpr (B % 8 == 0) {
+#pragma unroll
+        for (int c = 0; c < B / 8; c++) reinterpret_cast<uint2 *>(dst)[c] = reinterpret_cast<const uint2 *>(src)[c];
+    } else {
+#pragma unroll
+        for (int m = 0; m < N; m++) dst[m] = src[m];
+    }
+}
+template <typename T, int N>
+__device__ __forceinline__ void st_run(T *__restrict__ dst, const T (&src)[N]) {
+    constexpr int B = N * (int)sizeof(T);
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int c = 0; c < B / 16; c++) reinterpret_cast<uint4 *>(dst)[c] = reinterpret_cast<const uint4 *>(src)[c];
+    } else if constexpr (B % 8 == 0) {
+#pragma unroll
+        for (int c = 0; c < B / 8; c++) reinterpret_cast<uint2 *>(dst)[c] = reinterpret_cast<const uint2 *>(src)[c];
+    } else {
+#pragma unroll
+        for (int m = 0; m < N; m++) dst[m] = src[m];
+    }
+}
+
 struct Spacing {
     double ih2[3];
     double lam;   // Helmholtz term
@@ -347,16 +378,17 @@ __global__ void __launch_bounds__(256 * WIDE) k_gsrb(Plane<T> P, DevTables tb, i
         st_o.load(P.v + b * g::NC + oc * g::NH);
         st_g.load(P.vg + b * g::NG + oc * HF);
     }
+    // each thread updates IT consecutive cells of this colour: f (and eps) are read and
+    // v written as vectors
+    const int qt = q0 + tid * IT;
     T fr[IT], er[VAR ? IT : 1];
-#pragma unroll
-    for (int m = 0; m < IT; m++) fr[m] = P.f[b * g::NC + colour * g::NH + q0 + tid + m * TPB];
+    ld_run<T, IT>(P.f + b * g::NC + colour * g::NH + qt, fr);
     Stager<T, 1, VAR ? g::NH : 8, 0, TPB> st_eo;
     Stager<T, 2 * D, VAR ? HF : 8, g::NF, TPB> st_eg;
     if (VAR) {
         st_eo.load(P.eps + b * g::NC + oc * g::NH);
         st_eg.load(P.epsg + b * g::NG + oc * HF);
-#pragma unroll
-        for (int m = 0; m < IT; m++) er[m] = P.eps[b * g::NC + colour * g::NH + q0 + tid + m * TPB];
+        if constexpr (VAR) ld_run<T, IT>(P.eps + b * g::NC + colour * g::NH + qt, er);
     }
     BlockCtx<D> cx;
     cx.load(tb, b, lev);
@@ -386,9 +418,10 @@ __global__ void __launch_bounds__(256 * WIDE) k_gsrb(Plane<T> P, DevTables tb, i
     T ih2[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) ih2[a] = a < D ? T(1.0 / (cx.h[a] * cx.h[a])) : T(0);
+    T nvs[IT];
 #pragma unroll
     for (int m = 0; m < IT; m++) {
-        const int q = q0 + tid + m * TPB;
+        const int q = qt + m;
         const int row = q / g::RH, pos = q % g::RH;
         const int j = row % BS, k = D == 3 ? row / BS : 0;
         const int i = 2 * pos + ((j + k + colour) & 1);
@@ -432,9 +465,16 @@ __global__ void __launch_bounds__(256 * WIDE) k_gsrb(Plane<T> P, DevTables tb, i
                 den += w;
             }
         }
-        const T nv = (num - fval) / den;
-        P.v[b * g::NC + colour * g::NH + q] = nv;
-        push_ghosts<T, D, BS>(P.vg, cx, b, i, j, k, nv);
+        nvs[m] = (num - fval) / den;
+    }
+    st_run<T, IT>(P.v + b * g::NC + colour * g::NH + qt, nvs);
+#pragma unroll
+    for (int m = 0; m < IT; m++) {
+        const int q = qt + m;
+        const int row = q / g::RH, pos = q % g::RH;
+        const int j = row % BS, k = D == 3 ? row / BS : 0;
+        const int i = 2 * pos + ((j + k + colour) & 1);
+        push_ghosts<T, D, BS>(P.vg, cx, b, i, j, k, nvs[m]);
     }
 }
 
