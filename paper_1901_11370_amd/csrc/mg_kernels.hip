@@ -881,12 +881,21 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
     constexpr int ITB = (NBOX + TPB - 1) / TPB;
     constexpr int IT = (NPASS + TPB - 1) / TPB;
     const TailGeo tg = tail_geo(tb, dm, nt - 1, D);
-    // issue all loads first: the fine values this thread updates, then the staged box
+    // issue all loads first: the fine values this thread updates (a run of IT
+    // consecutive cells, read as vectors, when the pass divides evenly and the values
+    // are FP32), then the box
+    // (FP32 only: for FP64 the strided form, one 512-byte span per wave and load, is
+    // faster)
+    constexpr bool RUN = NPASS % TPB == 0 && sizeof(T) == 4;
     T vr[IT];
+    if constexpr (RUN) {
+        ld_run<T, IT>(P.v + b * g::NC + t0 + tid * IT, vr);
+    } else {
 #pragma unroll
-    for (int m = 0; m < IT; m++) {
-        const int u = tid + m * TPB;
-        vr[m] = P.v[b * g::NC + t0 + (NPASS % TPB == 0 || u < NPASS ? u : 0)];
+        for (int m = 0; m < IT; m++) {
+            const int u = tid + m * TPB;
+            vr[m] = P.v[b * g::NC + t0 + (u < NPASS ? u : 0)];
+        }
     }
     // box cell -> addresses of v and v_old (edges and corners of the halo, never
     // used, read the box centre instead)
@@ -922,7 +931,7 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
     }
     __syncthreads();
     if (!((mask >> dm) & 1)) return;
-    auto update = [&](int t, T vold) {
+    auto corrected = [&](int t, T vold) -> T {
         int i, j, k;
         g::decode(t, i, j, k);
         const int x = (i >> 1) + 1, y = (j >> 1) + 1, z = D == 3 ? (k >> 1) + 1 : 0;
@@ -932,15 +941,32 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
         T corr;
         if (D == 2) corr = T(0.25) * (T(2) * d0 + dx + dy);
         else corr = T(0.25) * (d0 + dx + dy + s_d[c0 + sz * HP * HP]);
-        const T nv = vold + corr;
-        P.v[b * g::NC + t] = nv;
+        return vold + corr;
+    };
+    auto push = [&](int t, T nv) {
+        int i, j, k;
+        g::decode(t, i, j, k);
         push_ghosts<T, D, BS>(P.vg, cx, b, i, j, k, nv);
     };
+    auto update = [&](int t, T vold) {
+        const T nv = corrected(t, vold);
+        P.v[b * g::NC + t] = nv;
+        push(t, nv);
+    };
+    if constexpr (RUN) {
+        T nvs[IT];
 #pragma unroll
-    for (int m = 0; m < IT; m++) {
-        const int u = tid + m * TPB;
-        if (NPASS % TPB != 0 && u >= NPASS) break;
-        update(t0 + u, vr[m]);
+        for (int m = 0; m < IT; m++) nvs[m] = corrected(t0 + tid * IT + m, vr[m]);
+        st_run<T, IT>(P.v + b * g::NC + t0 + tid * IT, nvs);
+#pragma unroll
+        for (int m = 0; m < IT; m++) push(t0 + tid * IT + m, nvs[m]);
+    } else {
+#pragma unroll
+        for (int m = 0; m < IT; m++) {
+            const int u = tid + m * TPB;
+            if (u >= NPASS) break;
+            update(t0 + u, vr[m]);
+        }
     }
     if (HALF) {
         bool phys = false;

@@ -34,7 +34,7 @@ def _one_cell(dim, kinds, lam=0.0, values=None):
     o = OracleTree(dim, n, [0.0] * dim, [1.0 * 16] * dim, kinds, bc_value=values, bs=16)
     if lam:
         o.set_lambda(lam)
-    assert o.level_info(0)[1][:dim] == (1,) * dim   # one cell of width 16 / 1 = 16? (h below)
+    assert o.level_info(0)[1][:dim] == (1,) * dim   # the coarsest grid is a single cell
     return o
 
 
