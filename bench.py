@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE_JSON = os.path.join(ROOT, "profiles", "gsrb_fp64_poisson3d_256_counters.json")
+PROFILE_JSON = os.path.join(ROOT, "profiles", "finest_sweep_counters.json")
 
 
 def _args():
@@ -75,25 +75,27 @@ def copy_calibration(mib):
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources (kernels, launchers and the structures they take)."""
     h = hashlib.sha256()
-    for f in ("mg_kernels.hip", "mg_api.cpp", "mg_internal.hpp"):
+    for f in ("mg_kernels.hip", "mg_internal.hpp"):
         with open(os.path.join(ROOT, "paper_1901_11370_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(n_cells):
-    """HBM bytes per launch of the finest-level FP64 smoothing kernel from committed
-    rocprofv3 counter runs (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
-    calibration); None when absent or taken on other kernel sources."""
+def traffic_from_profile(key, n_cells):
+    """HBM bytes per launch of a finest-level smoothing kernel from committed rocprofv3
+    counter runs (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration);
+    None when absent, taken on other kernel sources or on another level size."""
     try:
         with open(PROFILE_JSON) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("source_hash") != kernel_source_hash() or d.get("n_cells") != n_cells:
+    e = d.get("entries", {}).get(key)
+    if d.get("source_hash") != kernel_source_hash() or not e or e.get("n_cells") != n_cells:
         return None
-    return d.get("bytes_per_launch")
+    return e.get("bytes_per_launch")
 
 
 MAX_CYCLES = 60
@@ -587,8 +589,9 @@ def report(a):
         return
 
 
-def roofline_of(prof, kernel, dtp):
-    """Roofline record of the event-timed finest-level smoothing launches."""
+def roofline_of(prof, kernel, dtp, key=None, n_cells=None):
+    """Roofline record of the event-timed finest-level smoothing launches; `traffic` from
+    the counter runs stored under `key` for a finest level of n_cells cells."""
     launches, total_ms, bytes_per = prof
     if not launches:
         return None
@@ -596,7 +599,14 @@ def roofline_of(prof, kernel, dtp):
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "kernel": kernel, "avg_us": avg_ms * 1e3, "launches": launches,
-            "algorithmic_bytes_per_launch": bytes_per, "events_region_ms_per_step": dtp * 1e3}
+            "algorithmic_bytes_per_launch": bytes_per, "events_region_ms_per_step": dtp * 1e3,
+            "traffic": traffic_from_profile(key, n_cells) if key else None}
+
+
+def _finest_cells(t):
+    """Cells of the tree's finest level (the level whose sweeps the roofline times)."""
+    _, ncell = t.level_blocks()
+    return int(ncell[-1])
 
 
 def amr_leg(a, mg, W):
@@ -618,7 +628,7 @@ def amr_leg(a, mg, W):
                "cycles": cyc[-1], "converged": all(rc == 0 for rc in rcs), "final_rel_residual": float(r[-1]),
                "leaf_cell_cycles_per_s": t.n_leaf * cyc[-1] / dt, "leaf_cells": t.n_leaf,
                "roofline": roofline_of(prof, f"k_gsrb<{'double' if prec == 0 else 'float'},3,16> finest AMR level "
-                                             "(one colour)", dtp)}
+                                             "(one colour)", dtp, f"amr_nested_{key}", _finest_cells(t))}
         if key == "fp64":
             phi64 = t.get_phi()
         else:
@@ -661,7 +671,8 @@ def batch_leg(a, mg, W):
     out = {"workload": "diffsolve3d_batch6 (64^3..256^3, log-normal eps), J = 1/2 |phi - phi_t|^2",
            "leaf_cells": t.n_leaf, "fwd_bwd_ms": dt * 1e3, "fwd_bwd_ms_median_events": _median(per) * 1e3,
            "forward_ms": dtf * 1e3, "forward_ir_steps": cyc[-1], "forward_converged": all(rc == 0 for rc in rcs),
-           "roofline": roofline_of(prof, "k_gsrb<float,3,16,var-eps> finest level (one colour)", dtp)}
+           "roofline": roofline_of(prof, "k_gsrb<float,3,16,var-eps> finest level (one colour)", dtp,
+                                   "diffsolve_batch_fp32", _finest_cells(t))}
     del t
     torch.cuda.empty_cache()
     return out
@@ -743,9 +754,9 @@ def main():
         "final_rel_residual": float(res[-1]),
         "gs_point_updates_per_s": gs_updates / dt,
     }
-    roof = roofline_of(prof, "k_gsrb<double,3,16> finest level (one colour)", dtp)
+    roof = roofline_of(prof, "k_gsrb<double,3,16> finest level (one colour)", dtp, "poisson3d_256_fp64",
+                       int(ncell[-1]))
     if roof:
-        roof["traffic"] = traffic_from_profile(int(ncell[-1]))
         roof["copy_gbs_in_run"] = copy_bandwidth()
         roof["frac_of_copy"] = roof["achieved"] / roof["copy_gbs_in_run"]
         out["roofline"] = roof
@@ -765,7 +776,8 @@ def main():
                         "value": n_leaf * cycm[-1] / dtm, "unit": "cell-updates/s",
                         "speedup_vs_fp64": dt / dtm,
                         "rel_diff_vs_fp64_solution": float(np.abs(pm - p64).max() / np.abs(p64).max()),
-                        "roofline": roofline_of(profm, "k_gsrb<float,3,16> finest level (one colour)", dtmp)}
+                        "roofline": roofline_of(profm, "k_gsrb<float,3,16> finest level (one colour)", dtmp,
+                                                "poisson3d_256_fp32", int(ncell[-1]))}
         del tmx
     del t64
     torch.cuda.empty_cache()

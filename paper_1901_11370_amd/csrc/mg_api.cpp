@@ -504,12 +504,20 @@ struct Driver {
             vcycle(l, m);
         }
     }
-    // Parents take the mean of their children, then ghosts from coarse to fine.
-    void sync() {
+    // Parents take the mean of their children, then ghosts from coarse to fine.  With
+    // pushed set, every same-level and boundary ghost is already current (the last
+    // kernel to change each cell pushed it: after a cycle, or after a leaf update that
+    // pushes) and the restriction pushes the parents' new values, so only the
+    // coarse-fine ghosts are recomputed; otherwise every ghost is.  Both give the same
+    // values.
+    void sync(bool pushed = false) {
         const int nt = t->T.nt, top = t->T.nlev - 1;
         const uint64_t all = all_mask(t);
         for (int l = top; l > nt; l--) K<T>::restrict_down(L, P, l, lvb0(t, l), lvnb(t, l), all, RESTRICT_V, false);
-        for (int l = nt; l <= top; l++) ghost_level(l, all);
+        for (int l = nt; l <= top; l++) {
+            if (pushed) cf_refresh(l, all);
+            else ghost_level(l, all);
+        }
     }
 };
 
@@ -518,11 +526,13 @@ Driver<float> d32(mg_tree *t) { return Driver<float>{t, launch(t, true), t->P32,
 
 // FP64 composite residual (per-domain norms in d_domnorms); r may be written into the
 // FP32 right-hand side; with copy_out the norms are copied to the pinned host buffer.
-void enq_residual(mg_tree *t, bool write_r32, bool copy_out) {
+// after_cycle: the FP64 values were last changed by a cycle or by launch_add_leaf in
+// the same sequence, so their same-level and boundary ghosts are current.
+void enq_residual(mg_tree *t, bool write_r32, bool copy_out, bool after_cycle = false) {
     Driver<double> D = d64(t);
     // Without refinement the leaf residual uses only same-level and boundary ghosts,
     // which every kernel keeps current; parents enter only through coarse-fine ghosts.
-    if (t->T.refined) D.sync();
+    if (t->T.refined) D.sync(after_cycle);
     launch_norm64(D.L, t->P64, (int)t->nleafblk, var(t), write_r32 ? t->P32.f : nullptr, nullptr);
     if (copy_out) D.L.host_norms = t->d_hnorms;   // the reduction writes the pinned host buffer too
     launch_reduce_norms(D.L);
@@ -645,7 +655,7 @@ void ir_enqueue(mg_tree *t, bool use_fmg, bool defer_add = false) {
 void enq_add_residual(mg_tree *t, bool write_r32, bool copy_out) {
     if (t->T.refined) {
         launch_add_leaf(launch(t, t->homog), t->P64.v, t->P64.vg, t->P32.v, (int)t->nleafblk);
-        enq_residual(t, write_r32, copy_out);
+        enq_residual(t, write_r32, copy_out, true);
         return;
     }
     Driver<double> D = d64(t);
@@ -1290,7 +1300,7 @@ int mg_solve(mg_tree *t, double rel_tol, int max_cycles, int use_fmg_first, int 
         if (use_fmg_first && max_cycles > 0) {
             rc = run_seq(t, G_FMG_NORM, [&] {
                 d64(t).fmg();
-                enq_residual(t, false, true);
+                enq_residual(t, false, true, true);
             });
             cycles++;
         } else {
@@ -1305,7 +1315,7 @@ int mg_solve(mg_tree *t, double rel_tol, int max_cycles, int use_fmg_first, int 
             if (rel <= rel_tol || cycles >= max_cycles) break;
             if ((rc = run_seq(t, G_V_NORM, [&] {
                      d64(t).vcycle(top, all);
-                     enq_residual(t, false, true);
+                     enq_residual(t, false, true, true);
                  })))
                 return rc;
             cycles++;
