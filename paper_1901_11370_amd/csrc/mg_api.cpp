@@ -37,7 +37,8 @@ struct mg_tree {
     uint64_t tail_lds[2] = {0, 0};  // domains whose coarse grids fit in LDS (FP64, FP32)
     Plane<double> P64{};
     Plane<float> P32{};
-    std::vector<int32_t *> d_parents, d_cfs;
+    std::vector<int32_t *> d_parents, d_cff;
+    std::vector<std::vector<int32_t>> cf_faces;   // per level: 8 b + f of each coarse-fine face
     double *d_stage = nullptr, *d_stage2 = nullptr;
     int32_t *d_steps = nullptr;
     double *d_partials = nullptr, *d_domnorms = nullptr;
@@ -128,10 +129,16 @@ size_t plan(mg_tree *t, char *base) {
     size_t o_toff = L.take<int64_t>((size_t)T.ndom * MAXLEV);
     size_t o_ttop = L.take<int32_t>(T.ndom);
     size_t o_lox = L.take<double>(T.ndom);
-    std::vector<size_t> o_parl(T.nlev), o_cfl(T.nlev);
+    // per level the (block, face) pairs with a coarse neighbour, as 8 b + f
+    t->cf_faces.assign(T.nlev, {});
+    for (int l = 0; l < T.nlev; l++)
+        for (int32_t b : T.cf_of_level[l])
+            for (int f = 0; f < 2 * T.dim; f++)
+                if (T.nbr[6 * (size_t)b + f] == -2) t->cf_faces[l].push_back(8 * b + f);
+    std::vector<size_t> o_parl(T.nlev), o_cff(T.nlev);
     for (int l = 0; l < T.nlev; l++) {
         o_parl[l] = L.take<int32_t>(T.parents_of_level[l].size());
-        o_cfl[l] = L.take<int32_t>(T.cf_of_level[l].size());
+        o_cff[l] = L.take<int32_t>(t->cf_faces[l].size());
     }
     t->off_tables = 0;
     t->bytes_tables = L.off;
@@ -170,7 +177,7 @@ size_t plan(mg_tree *t, char *base) {
         put(o_lox, lox.data(), lox.size() * 8);
         for (int l = 0; l < T.nlev; l++) {
             put(o_parl[l], T.parents_of_level[l].data(), T.parents_of_level[l].size() * 4);
-            put(o_cfl[l], T.cf_of_level[l].data(), T.cf_of_level[l].size() * 4);
+            put(o_cff[l], t->cf_faces[l].data(), t->cf_faces[l].size() * 4);
         }
         DevTables &tb = t->tb;
         tb.org = (const int32_t *)P(o_org);
@@ -194,10 +201,10 @@ size_t plan(mg_tree *t, char *base) {
         t->tb0 = tb;
         t->tb0.bcv = (const double *)P(o_bc0);
         t->d_parents.assign(T.nlev, nullptr);
-        t->d_cfs.assign(T.nlev, nullptr);
+        t->d_cff.assign(T.nlev, nullptr);
         for (int l = 0; l < T.nlev; l++) {
             t->d_parents[l] = (int32_t *)P(o_parl[l]);
-            t->d_cfs[l] = (int32_t *)P(o_cfl[l]);
+            t->d_cff[l] = (int32_t *)P(o_cff[l]);
         }
     }
     // fields
@@ -342,7 +349,7 @@ struct Driver {
                 Dp.vg = dstg;
                 Dp.vc = P.v;
                 Dp.vcg = P.vg;
-                K<T>::ghost(L, Dp, 0, 0, t->d_cfs[l], ncf, m, false, true);
+                K<T>::cf_ghost(L, Dp, t->d_cff[l], (int)t->cf_faces[l].size(), m);
             }
         }
         if (steps & 1) {
@@ -383,8 +390,8 @@ struct Driver {
     }
     // Coarse-fine ghosts of level l from the current fine and coarse values.
     void cf_refresh(int l, uint64_t m) {
-        const int ncf = (int)t->T.cf_of_level[l].size();
-        if (ncf) K<T>::ghost(L, P, 0, 0, t->d_cfs[l], ncf, m, false, true);
+        const int nf = (int)t->cf_faces[l].size();
+        if (nf) K<T>::cf_ghost(L, P, t->d_cff[l], nf, m);
     }
     // The restriction pushes the parents' new boundary values into the ghosts of
     // level l-1; the other ghosts of that level are unchanged since its last update.

@@ -102,6 +102,7 @@ struct K {
                      uint64_t mask, bool var, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool zero = false);
     static void ghost(const Launch &L, const Plane<T> &P, int b0, int nb, const int32_t *list,
                       int nlist, uint64_t mask, bool eps_field, bool cf_only);
+    static void cf_ghost(const Launch &L, const Plane<T> &P, const int32_t *faces, int nfaces, uint64_t mask);
     static void restrict_down(const Launch &L, const Plane<T> &P, int lev, int b0, int nb,
                               uint64_t mask, int mode, bool var);
     static void fas(const Launch &L, const Plane<T> &P, int lev, const int32_t *list, int nlist,

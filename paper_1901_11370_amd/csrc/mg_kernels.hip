@@ -574,6 +574,59 @@ __global__ void __launch_bounds__(256) k_jacobi(Plane<T> P, T *__restrict__ dst,
 // tangential position by the central-difference slope(s) of the coarse cell and
 // c' = (3c - c2)/2 the two-point extrapolation of the fine cells to the face.  For the
 // eps field: copy, copy of the interior cell, and the coarse cell's value.
+// Coarse-fine ghost (face f of block b at level lv of domain dm, tangential position
+// a1, a2; qb the coarse block across the face, org the block's origin): the coarse cell
+// B moved to the ghost's tangential position by the central differences of the coarse
+// values, averaged with the two-point extrapolation (3c - c2)/2 of the fine cells c, c2
+// next to the face (Sec. 2.6, refinement boundaries).  For eps: the coarse cell.
+template <typename T, int D, int BS, bool EPS>
+__device__ __forceinline__ T cf_ghost_value(const Plane<T> &P, const DevTables &tb, int64_t b, int f, int a1,
+                                            int a2, int dm, int lv, int64_t qb, const int org[3]) {
+    using g = G<D, BS>;
+    const T *v = EPS ? P.eps : P.v;
+    const int a = f >> 1, side = f & 1;
+    const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+    int in1[3], in2[3];
+    in1[t1] = a1; in1[t2] = a2; in1[a] = side ? BS - 1 : 0;
+    in2[t1] = a1; in2[t2] = a2; in2[a] = side ? BS - 2 : 1;
+    if (D == 2) { in1[2] = 0; in2[2] = 0; }
+    T out;
+    int gi[3];
+    for (int c = 0; c < 3; c++) gi[c] = org[c] + in1[c];
+    gi[a] += side ? 1 : -1;
+    // wrap across a periodic face (the coarse region may lie beyond it)
+    const int32_t *nc = tb.ncell + ((size_t)dm * MAXLEV + lv) * 3;
+    if (gi[a] < 0) gi[a] += nc[a];
+    if (gi[a] >= nc[a]) gi[a] -= nc[a];
+    int cl[3];
+    for (int c = 0; c < 3; c++) cl[c] = (gi[c] >> 1) - tb.org[3 * qb + c];
+    if (D == 2) cl[2] = 0;
+    const T *w = EPS ? P.eps : (P.vc ? P.vc : P.v);
+    const T *wg = EPS ? P.epsg : (P.vcg ? P.vcg : P.vg);
+    T B = w[qb * g::NC + g::in(cl[0], cl[1], cl[2])];
+    if (EPS) {
+        out = B;
+    } else {
+        T Bp = B;
+        int tang[2] = {t1, t2};
+#pragma unroll
+        for (int m = 0; m < D - 1; m++) {
+            int td = tang[m];
+            T sigma = (gi[td] & 1) ? T(1) : T(-1);
+            int cp[3] = {cl[0], cl[1], cl[2]}, cm[3] = {cl[0], cl[1], cl[2]};
+            cp[td] += 1;
+            cm[td] -= 1;
+            T up = ld<D, BS>(w, wg, qb, cp[0], cp[1], cp[2]);
+            T dn = ld<D, BS>(w, wg, qb, cm[0], cm[1], cm[2]);
+            Bp += sigma * (up - dn) / T(8);
+        }
+        T c = v[b * g::NC + g::in(in1[0], in1[1], in1[2])];
+        T c2 = v[b * g::NC + g::in(in2[0], in2[1], in2[2])];
+        out = T(0.5) * (Bp + (T(1.5) * c - T(0.5) * c2));
+    }
+    return out;
+}
+
 template <typename T, int D, int BS, bool EPS>
 __device__ void ghost_cell(const Plane<T> &P, const DevTables &tb, int64_t b, int f, int a1, int a2,
                            bool cf_only) {
@@ -583,12 +636,11 @@ __device__ void ghost_cell(const Plane<T> &P, const DevTables &tb, int64_t b, in
     const int a = f >> 1, side = f & 1;
     const int n = tb.nbr[6 * b + f];
     if (cf_only && n != -2) return;
-    int in1[3], in2[3];
+    int in1[3];
     // tangential axes in increasing order
     const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
     in1[t1] = a1; in1[t2] = a2; in1[a] = side ? BS - 1 : 0;
-    in2[t1] = a1; in2[t2] = a2; in2[a] = side ? BS - 2 : 1;
-    if (D == 2) { in1[2] = 0; in2[2] = 0; }
+    if (D == 2) in1[2] = 0;
     T out;
     if (n >= 0) {
         int q[3] = {in1[0], in1[1], in1[2]};
@@ -609,42 +661,8 @@ __device__ void ghost_cell(const Plane<T> &P, const DevTables &tb, int64_t b, in
             out = bc_ghost<T>(tb.bck[6 * dm + f], bv, hh[a], side, ci);
         }
     } else {
-        const int dm = tb.dom[b];
-        const int lv = tb.lev[b];
-        const int64_t qb = tb.cf[6 * b + f];
-        int gi[3];
-        for (int c = 0; c < 3; c++) gi[c] = tb.org[3 * b + c] + in1[c];
-        gi[a] += side ? 1 : -1;
-        // wrap across a periodic face (the coarse region may lie beyond it)
-        const int32_t *nc = tb.ncell + ((size_t)dm * MAXLEV + lv) * 3;
-        if (gi[a] < 0) gi[a] += nc[a];
-        if (gi[a] >= nc[a]) gi[a] -= nc[a];
-        int cl[3];
-        for (int c = 0; c < 3; c++) cl[c] = (gi[c] >> 1) - tb.org[3 * qb + c];
-        if (D == 2) cl[2] = 0;
-        const T *w = EPS ? P.eps : (P.vc ? P.vc : P.v);
-        const T *wg = EPS ? P.epsg : (P.vcg ? P.vcg : P.vg);
-        T B = w[qb * g::NC + g::in(cl[0], cl[1], cl[2])];
-        if (EPS) {
-            out = B;
-        } else {
-            T Bp = B;
-            int tang[2] = {t1, t2};
-#pragma unroll
-            for (int m = 0; m < D - 1; m++) {
-                int td = tang[m];
-                T sigma = (gi[td] & 1) ? T(1) : T(-1);
-                int cp[3] = {cl[0], cl[1], cl[2]}, cm[3] = {cl[0], cl[1], cl[2]};
-                cp[td] += 1;
-                cm[td] -= 1;
-                T up = ld<D, BS>(w, wg, qb, cp[0], cp[1], cp[2]);
-                T dn = ld<D, BS>(w, wg, qb, cm[0], cm[1], cm[2]);
-                Bp += sigma * (up - dn) / T(8);
-            }
-            T c = v[b * g::NC + g::in(in1[0], in1[1], in1[2])];
-            T c2 = v[b * g::NC + g::in(in2[0], in2[1], in2[2])];
-            out = T(0.5) * (Bp + (T(1.5) * c - T(0.5) * c2));
-        }
+        const int org[3] = {tb.org[3 * b], tb.org[3 * b + 1], tb.org[3 * b + 2]};
+        out = cf_ghost_value<T, D, BS, EPS>(P, tb, b, f, a1, a2, tb.dom[b], tb.lev[b], tb.cf[6 * b + f], org);
     }
     vg[b * g::NG + g::gh(f, a1, a2)] = out;
 }
@@ -659,6 +677,26 @@ __global__ void __launch_bounds__(256) k_ghost(Plane<T> P, DevTables tb, int b0,
         int f = t / g::NF, r = t % g::NF;
         ghost_cell<T, D, BS, EPS>(P, tb, b, f, r % BS, r / BS, cf_only != 0);
     }
+}
+
+// Coarse-fine ghosts of a list of (block, face) pairs (entry 8 b + f), one ghost cell
+// per thread: every thread issues its table loads at once and no thread idles on a
+// face without a coarse neighbour.
+template <typename T, int D, int BS>
+__global__ void __launch_bounds__(256) k_cf_ghost(Plane<T> P, DevTables tb, const int32_t *faces, int nfaces,
+                                                  uint64_t mask) {
+    using g = G<D, BS>;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)nfaces * g::NF) return;
+    const int32_t e = faces[t / g::NF];
+    const int64_t b = e >> 3;
+    const int f = e & 7;
+    const int r = (int)(t % g::NF);
+    const int dm = tb.dom[b], lv = tb.lev[b];
+    const int64_t qb = tb.cf[6 * b + f];
+    const int org[3] = {tb.org[3 * b], tb.org[3 * b + 1], tb.org[3 * b + 2]};
+    const T out = cf_ghost_value<T, D, BS, false>(P, tb, b, f, r % BS, r / BS, dm, lv, qb, org);
+    if ((mask >> dm) & 1) P.vg[b * g::NG + g::gh(f, r % BS, r / BS)] = out;
 }
 
 // ------------------------------------------------------ tail grid indexing
@@ -2615,6 +2653,16 @@ void K<T>::ghost(const Launch &L, const Plane<T> &P, int b0, int nb, const int32
         constexpr int TPB = NG < 256 ? NG : 256;
         if (eps_field) k_ghost<T, D, BS, true><<<n, TPB, 0, L.stream>>>(P, L.tb, b0, list, mask, cf_only);
         else k_ghost<T, D, BS, false><<<n, TPB, 0, L.stream>>>(P, L.tb, b0, list, mask, cf_only);
+    });
+}
+
+template <typename T>
+void K<T>::cf_ghost(const Launch &L, const Plane<T> &P, const int32_t *faces, int nfaces, uint64_t mask) {
+    if (nfaces <= 0) return;
+    DISPATCH_DB(L, {
+        constexpr int NF = G<D, BS>::NF;
+        const int64_t n = (int64_t)nfaces * NF;
+        k_cf_ghost<T, D, BS><<<(unsigned)((n + 255) / 256), 256, 0, L.stream>>>(P, L.tb, faces, nfaces, mask);
     });
 }
 

@@ -245,6 +245,8 @@ std::string build_tree(HostTree &T, const mg_domain *doms, int ndom, int bs, int
     }
     T.lev_first[T.nlev] = next;
     int nb = next;
+    // block indices travel as 8 b + face in the coarse-fine face lists
+    if (nb >= (1 << 28)) return "too many blocks (at most 2^28)";
     T.org.assign(3 * (size_t)nb, 0);
     T.nbr.assign(6 * (size_t)nb, -1);
     T.cf.assign(6 * (size_t)nb, -1);
