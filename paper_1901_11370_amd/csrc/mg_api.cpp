@@ -401,11 +401,12 @@ struct Driver {
             K<T>::fas(L, P, l - 1, t->d_parents[l - 1], (int)t->T.parents_of_level[l - 1].size(), m, v);
     }
     // The correction pushes same-level and boundary ghosts; coarse-fine ghosts follow.
-    // next_steps: smoothing steps that follow on level l; with red-black Gauss-Seidel
-    // and no coarse-fine faces the first half-sweep rewrites colour 0 without reading it,
-    // so only colour 1 needs the correction (blocks on physical faces excepted).
+    // next_steps: smoothing steps that follow on level l; with red-black Gauss-Seidel the
+    // first half-sweep rewrites colour 0 without reading it, so only colour 1 needs the
+    // correction, except in blocks with a physical or coarse-fine face, whose ghosts
+    // are computed from colour-0 cells before that half-sweep reads them.
     void correct(int l, uint64_t m, int next_steps) {
-        const bool half = next_steps > 0 && !jacobi(t) && !t->T.refined;
+        const bool half = next_steps > 0 && !jacobi(t);
         K<T>::correct(L, P, l, lvb0(t, l), lvnb(t, l), m, half);
         cf_refresh(l, m);
     }

@@ -886,11 +886,12 @@ __global__ void __launch_bounds__(256) k_fas(Plane<T> P, DevTables tb, int lev, 
 // halo is staged in LDS; the fine block is updated with unit stride and its boundary
 // values pushed into the mirroring ghosts.
 // (SPLIT workgroups per block on levels with few blocks, as for the smoothing.)
-// HALF: a red-black half-sweep of colour 0 follows on a level without coarse-fine
-// faces.  It reads only colour 1 and the colour-1 ghost halves and rewrites every
-// colour-0 cell and ghost, so only colour 1 is corrected -- except in blocks with a
-// physical face, whose colour-0 boundary cells are read through the ghosts that mirror
-// them (Dirichlet, Neumann): those blocks correct both colours.
+// HALF: a red-black half-sweep of colour 0 follows.  It reads only colour 1 and the
+// colour-1 ghost halves and rewrites every colour-0 cell (pushing its same-level
+// ghosts), so only colour 1 is corrected -- except in blocks with a physical face,
+// whose colour-0 boundary cells are read through the ghosts that mirror them
+// (Dirichlet, Neumann), or with a coarse-fine face, whose ghosts are extrapolated from
+// cells of both colours: those blocks correct both colours.
 template <typename T, int D, int BS, int SPLIT, bool HALF>
 __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int lev, int b0, uint64_t mask,
                                                  int nt) {
@@ -1007,10 +1008,12 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
         }
     }
     if (HALF) {
-        bool phys = false;
+        // blocks with a physical face (whose ghosts mirror colour-0 cells) or a
+        // coarse-fine face (whose ghosts extrapolate from both colours) are corrected whole
+        bool whole = false;
 #pragma unroll
-        for (int f = 0; f < 2 * D; f++) phys = phys || cx.nbr[f] == -1;
-        if (phys) {
+        for (int f = 0; f < 2 * D; f++) whole = whole || cx.nbr[f] < 0;
+        if (whole) {
 #pragma unroll
             for (int m = 0; m < IT; m++) {
                 const int u = tid + m * TPB;
