@@ -24,6 +24,8 @@ namespace mgx {
 // slowly converging grid may rise for a few steps before it falls).
 constexpr double kStall = 0.999;
 constexpr int kStallSteps = 8;
+// Coarsest grids of at most this many cells are iterated by one wave.
+constexpr int kWaveCoarse = 128;
 
 // Workgroups are dealt round-robin over the chip's 8 XCDs, each with its own L2.
 // Workgroup w of a launch over n blocks takes block xcd_block(w, n): XCD x gets a
@@ -1153,14 +1155,14 @@ struct Tail {
     }
     // The whole ghost layer of one grid (faces only): periodic copy or boundary
     // condition (for eps, a copy of the interior cell).
-    __device__ __forceinline__ void fill_ghosts(int lev, T *u, bool eps) const {
+    __device__ __forceinline__ void fill_ghosts(int lev, T *u, bool eps, int stride = NT) const {
         const TailLev g = lv[lev];
 #pragma unroll
         for (int a = 0; a < D; a++) {
             const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
             const int n1 = g.n[t1], n2 = D == 3 ? g.n[t2] : 1;
             const int tot = 2 * n1 * n2;
-            for (int q = threadIdx.x; q < tot; q += NT) {
+            for (int q = threadIdx.x; q < tot; q += stride) {
                 const int side = q >= n1 * n2;
                 const int r = q - side * n1 * n2;
                 int c[3], in[3], op[3];
@@ -1211,21 +1213,25 @@ struct Tail {
         return s - T(g.lam) * vc;
     }
 
-    // One colour of Gauss-Seidel on grid lev, then a barrier.
-    __device__ __forceinline__ void sweep(int lev, int colour) const {
+    // Orders the accesses of one wave (LDS and memory) where only that wave runs.
+    __device__ __forceinline__ void wave_fence() const { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+    // One colour of Gauss-Seidel on grid lev, then a barrier (wave: run by wave 0
+    // alone, a fence in place of the barrier).
+    __device__ __forceinline__ void sweep(int lev, int colour, bool wave = false) const {
         const TailLev g = lv[lev];
         const bool gp = g.ghost_pass;
         const int ns = nslot(g);
+        const int nt = wave ? 64 : NT;
         // Two slots per pass, every load of both issued before either store: a
         // half-sweep reads only the other colour, and a physical ghost it writes is
         // read only by the cell it mirrors, before that cell's update.
-        for (int s0 = threadIdx.x; s0 < ns; s0 += 2 * NT) {
+        for (int s0 = threadIdx.x; s0 < ns; s0 += 2 * nt) {
             int ii[2] = {0, 0}, jj[2] = {0, 0}, kk[2] = {0, 0}, oo[2] = {0, 0};
             bool ok[2];
             T fo[2], w[2][6], nb[2][6];
 #pragma unroll
             for (int u = 0; u < 2; u++) {
-                const int s = s0 + u * NT;
+                const int s = s0 + u * nt;
                 ok[u] = s < ns && slot(g, s, colour, ii[u], jj[u], kk[u]);
                 if (ok[u]) {
                     oo[u] = tix<D>(g, ii[u], jj[u], kk[u]);
@@ -1247,10 +1253,12 @@ struct Tail {
                 if (!gp) push(tv, g, ii[u], jj[u], kk[u], nv, true);
             }
         }
-        __syncthreads();
+        if (wave) wave_fence();
+        else __syncthreads();
         if (gp) {
-            fill_ghosts(lev, tv, false);
-            __syncthreads();
+            fill_ghosts(lev, tv, false, nt);
+            if (wave) wave_fence();
+            else __syncthreads();
         }
     }
     // Weighted Jacobi value of cell (i,j,k) from the current (old) values.
@@ -1325,11 +1333,12 @@ struct Tail {
 
     // Block-wide reductions (all threads get the result): wave shuffles, then one
     // exchange through LDS.
-    __device__ __forceinline__ double reduce_max(double x) const {
+    __device__ __forceinline__ double reduce_max(double x, bool wave = false) const {
         for (int o = 32; o > 0; o >>= 1) {
             double y = __shfl_xor(x, o);
             if (y > x || y != y) x = y;
         }
+        if (wave) return x;   // one wave only
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
         __syncthreads();
         x = red[0];
@@ -1348,16 +1357,16 @@ struct Tail {
         return x;
     }
 
-    __device__ __forceinline__ double resmax(int lev) const {
+    __device__ __forceinline__ double resmax(int lev, bool wave = false) const {
         const TailLev g = lv[lev];
         double m = 0.0;
-        for (int c = threadIdx.x; c < g.ncell; c += NT) {
+        for (int c = threadIdx.x; c < g.ncell; c += wave ? 64 : NT) {
             int i, j, k;
             cell(g, c, i, j, k);
             const double r = fabs((double)(tf[tix<D>(g, i, j, k)] - Lv(g, i, j, k)));
             if (r > m || r != r) m = r;
         }
-        return reduce_max(m);
+        return reduce_max(m, wave);
     }
 
     // dst = v on the padded grid g, two elements per pass (loads before stores; the
@@ -1486,21 +1495,37 @@ struct Tail {
             }
             __syncthreads();
         }
-        const double r0 = resmax(0);
-        double best = r0;
-        const double target = fmax(tp.abs_tol, tp.rel_tol * r0);
-        int k, since = 0;
-        for (k = 1; k <= tp.n_max; k++) {
-            smooth(0);
-            const double r = resmax(0);
-            if (r <= target) break;
-            if (r < kStall * best) {
-                best = r;
-                since = 0;
-            } else if (++since >= kStallSteps) {
-                break;
+        // A small grid (Gauss-Seidel) is iterated by wave 0 alone, its phases ordered
+        // by fences: cells of one colour read only the other colour, and a ghost a cell
+        // pushes is read in that half-sweep only by the cell itself (periodic axes of
+        // odd length are refilled after it), so the updates are those of the whole
+        // workgroup.  The other waves wait at the closing barrier; the step count is
+        // wave 0's, the one reported.
+        const bool wave = !jac && g.ncell <= kWaveCoarse;
+        int k = 0;
+        if (!wave || threadIdx.x < 64) {
+            const double r0 = resmax(0, wave);
+            double best = r0;
+            const double target = fmax(tp.abs_tol, tp.rel_tol * r0);
+            int since = 0;
+            for (k = 1; k <= tp.n_max; k++) {
+                if (wave) {
+                    sweep(0, 0, true);
+                    sweep(0, 1, true);
+                } else {
+                    smooth(0);
+                }
+                const double r = resmax(0, wave);
+                if (r <= target) break;
+                if (r < kStall * best) {
+                    best = r;
+                    since = 0;
+                } else if (++since >= kStallSteps) {
+                    break;
+                }
             }
         }
+        if (wave) __syncthreads();
         return k > tp.n_max ? tp.n_max : k;
     }
 
