@@ -1738,6 +1738,7 @@ __global__ void __launch_bounds__((tail_threads<VAR, D>())) k_tail(Plane<T> P, D
 template <typename T, int D>
 __global__ void __launch_bounds__(tail_threads<true>()) k_tail_eps(Plane<T> P, DevTables tb, int nt) {
     constexpr int NT = tail_threads<true>();
+    static_assert(NT == Tail<T, D, true>::NT, "the Tail methods called here stride by Tail::NT");
     __shared__ double red[16];
     __shared__ TailLev lvs[MAXLEV];
     __shared__ TailBC bcs;
