@@ -209,3 +209,35 @@ def test_fmg_from_the_far_field_guess(n):
     ec = np.sqrt(np.mean((t.get_phi() - exact) ** 2))
     print(f"n={n}: L2 error after 2 FMG {e2:.3e}, converged {ec:.3e}", flush=True)
     assert e2 < 1.3 * ec
+
+
+def _two_fmg_error(n, sources):
+    """L2 error against eq. gauss-sol after the guess and two FMG cycles, and once
+    converged to 1e-10, for a sum of Gaussian sources (offset, sign)."""
+    ws = [W.freespace_gauss((n,), offsets=[off]) for off, _ in sources]
+    t = gpu_tree(ws[0])
+    lay = t.leaf_layout()[:, 1:]
+    f = sum(s * w.rhs(0, lay) for (_, s), w in zip(sources, ws))
+    exact = sum(s * w.target(0, lay) for (_, s), w in zip(sources, ws))
+    t.set_rhs(f)
+    t.freespace_guess(1)
+    t.freespace_bc(1)
+    t.fmg(2)
+    e2 = np.sqrt(np.mean((t.get_phi() - exact) ** 2))
+    t.solve(rel_tol=1e-10, max_cycles=30, fmg_first=False)
+    ec = np.sqrt(np.mean((t.get_phi() - exact) ** 2))
+    return e2, ec, np.sqrt(np.mean(exact ** 2))
+
+
+@pytest.mark.parametrize("case", ["offcentre", "dipole"])
+def test_fmg_from_the_far_field_guess_other_sources(case):
+    # an off-centre source, whose far field the guess places at the charges' centroid,
+    # and two opposite charges, whose monopole guess is zero: two FMG cycles still reach
+    # the converged error
+    if case == "offcentre":
+        sources = [((0.12, -0.08, 0.1), 1.0)]
+    else:
+        sources = [((0.1, 0.0, 0.0), 1.0), ((-0.1, 0.0, 0.0), -1.0)]
+    e2, ec, scale = _two_fmg_error(128, sources)
+    print(f"{case}: L2 error after 2 FMG {e2:.3e}, converged {ec:.3e}, rms phi {scale:.3e}", flush=True)
+    assert e2 < 1.3 * ec
