@@ -24,8 +24,8 @@ namespace mgx {
 // slowly converging grid may rise for a few steps before it falls).
 constexpr double kStall = 0.999;
 constexpr int kStallSteps = 8;
-// Coarsest grids of at most this many cells are iterated by one wave.
-constexpr int kWaveCoarse = 128;
+// Coarsest grids of at most this many cells (one per lane) are iterated by one wave.
+constexpr int kWaveCoarse = 64;
 
 // Workgroups are dealt round-robin over the chip's 8 XCDs, each with its own L2.
 // Workgroup w of a launch over n blocks takes block xcd_block(w, n): XCD x gets a
