@@ -92,6 +92,9 @@ typedef struct {
                                  default 3: with a contraction of ~0.1 per cycle three
                                  cycles stay above the FP32 accuracy of the correction, and
                                  each step costs one FP64 residual and one host check).
+                                 mg_solve runs fewer in a step (at least one) when the
+                                 largest per-cycle reduction of the steps before says that
+                                 fewer reach rel_tol with a quarter cycle to spare.
                                  The FGMRES preconditioner is always one V-cycle. */
     int32_t graphs;           /* 1 (default): each cycle sequence (V-cycle, FMG cycle,
                                  refinement step, residual norm) is captured once as a

@@ -56,8 +56,8 @@ struct mg_tree {
     // captured cycle sequences (graph kind x homogeneous flag), replayed on `stream`
     hipStream_t cap = nullptr;       // capture stream (non-blocking, default priority)
     double *h_norms = nullptr;       // pinned host copy of the per-domain norms
-    hipGraphExec_t gexec[32] = {};
-    bool gfail[32] = {};
+    hipGraphExec_t gexec[64] = {};
+    bool gfail[64] = {};
     // profiling: event pairs around the finest-level smoothing launches (kernels are
     // then launched one by one, not replayed from graphs)
     bool prof = false;
@@ -556,8 +556,11 @@ int read_norms(mg_tree *t, std::vector<double> *norms) {
 // Kinds of captured sequences.
 enum {
     G_V = 0, G_FMG, G_V_NORM, G_FMG_NORM, G_NORM, G_NORM_R32, G_IRV_NORM, G_IRFMG_NORM, G_IRV_FULL, G_IRFMG_FULL,
-    G_KINDS
+    G_IRV_FEWER,                       // G_IRV_NORM with 1 ... kIrFewer V-cycles (kinds G_IRV_FEWER + n - 1)
+    G_KINDS = G_IRV_FEWER + 8
 };
+constexpr int kIrFewer = G_KINDS - G_IRV_FEWER;
+static_assert(2 * G_KINDS <= 64, "graph slots");
 
 void drop_graphs(mg_tree *t) {
     for (auto &g : t->gexec) {
@@ -631,7 +634,7 @@ int worst(const mg_tree *t, const std::vector<double> &n, double *mx, double *l2
 // One refinement step's correction: FP32 cycle(s) on L e = r (r in the FP32 right-hand
 // side, e from zero), then phi += e unless the caller fuses that with the next residual
 // (enq_add_residual).
-void ir_enqueue(mg_tree *t, bool use_fmg, bool defer_add = false) {
+void ir_enqueue(mg_tree *t, bool use_fmg, bool defer_add = false, int n_v = 0) {
     Driver<float> D = d32(t);
     const Plane<float> &P = t->P32;
     // A V-cycle from e = 0 on a tree whose leaves are all on the top level (of every
@@ -651,7 +654,8 @@ void ir_enqueue(mg_tree *t, bool use_fmg, bool defer_add = false) {
     if (use_fmg) {
         D.fmg();
     } else {
-        for (int c = 0; c < std::max(1, t->prm.ir_vcycles); c++) D.vcycle(t->T.nlev - 1, all_mask(t));
+        const int nv = n_v > 0 ? n_v : std::max(1, t->prm.ir_vcycles);
+        for (int c = 0; c < nv; c++) D.vcycle(t->T.nlev - 1, all_mask(t));
     }
     if (defer_add) return;
     Launch L64 = launch(t, t->homog);
@@ -1335,18 +1339,34 @@ int mg_solve(mg_tree *t, double rel_tol, int max_cycles, int use_fmg_first, int 
         }
     } else {
         if ((rc = run_seq(t, G_NORM_R32, [&] { enq_residual(t, true, true); }))) return rc;
+        // rho: the largest residual reduction per V-cycle seen in the plain steps so far.
+        // A step runs fewer than ir_vcycles V-cycles when, at that rate and with a margin
+        // of a quarter cycle, fewer reach rel_tol (typically the last step).
+        double prev = INFINITY, rho = 0.0;
+        int prev_nv = 0;
         for (;;) {
             if ((rc = read_norms(t, &n))) return rc;
             rc = worst(t, n, &rel, nullptr);
             record(rel);
             if (rc) break;
+            if (prev_nv > 0 && rel > 0.0 && prev > 0.0 && std::isfinite(prev))
+                rho = std::max(rho, std::pow(rel / prev, 1.0 / prev_nv));
             if (rel <= rel_tol || cycles >= max_cycles) break;
             const bool f = cycles == 0 && use_fmg_first && t->prm.ir_first_fmg;
-            if ((rc = run_seq(t, f ? G_IRFMG_NORM : G_IRV_NORM, [&] {
-                     ir_enqueue(t, f, true);
+            int nv = std::max(1, t->prm.ir_vcycles);
+            if (!f && rho > 0.0 && rho < 1.0 && rel_tol > 0.0) {
+                const double need = std::log(rel_tol / rel) / std::log(rho);
+                const int k = (int)std::ceil(need + 0.25);
+                if (k >= 1 && k < nv && k <= kIrFewer) nv = k;
+            }
+            const int kind = f ? G_IRFMG_NORM : nv == std::max(1, t->prm.ir_vcycles) ? G_IRV_NORM : G_IRV_FEWER + nv - 1;
+            if ((rc = run_seq(t, kind, [&] {
+                     ir_enqueue(t, f, true, f ? 0 : nv);
                      enq_add_residual(t, true, true);
                  })))
                 return rc;
+            prev = rel;
+            prev_nv = f ? 0 : nv;
             cycles++;
         }
     }
