@@ -89,9 +89,10 @@ typedef struct {
     int32_t variable_eps;     /* 0: eps = 1, constant-coefficient stencil; 1: eps field */
     int32_t ir_first_fmg;     /* mixed: the first refinement step runs an FP32 FMG cycle */
     int32_t ir_vcycles;       /* mixed: FP32 V-cycles per plain refinement step (>= 1;
-                                 default 3: with a contraction of ~0.1 per cycle three
-                                 cycles stay above the FP32 accuracy of the correction, and
-                                 each step costs one FP64 residual and one host check).
+                                 default 4: with a contraction of ~0.1 per cycle four
+                                 cycles (~1e-4) stay above the FP32 accuracy of the
+                                 correction, and each step costs one FP64 residual and one
+                                 host check).
                                  mg_solve runs fewer in a step (at least one) when the
                                  largest per-cycle reduction of the steps before says that
                                  fewer reach rel_tol with a quarter cycle to spare.

@@ -844,7 +844,7 @@ int mg_default_params(mg_params *p) {
     p->precision = MG_FP64;
     p->variable_eps = 0;
     p->ir_first_fmg = 1;
-    p->ir_vcycles = 3;
+    p->ir_vcycles = 4;
     p->graphs = 1;
     p->krylov = 0;
     p->smoother = MG_SMOOTH_GSRB;
