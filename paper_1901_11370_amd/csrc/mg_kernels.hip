@@ -420,6 +420,13 @@ __global__ void __launch_bounds__(256 * WIDE) k_gsrb(Plane<T> P, DevTables tb, i
     T ih2[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) ih2[a] = a < D ? T(1.0 / (cx.h[a] * cx.h[a])) : T(0);
+    // constant coefficient (Cartesian): one diagonal for the whole block, so one
+    // reciprocal in place of a division per cell
+    T dconst = T(tb.lambda);
+#pragma unroll
+    for (int a = 0; a < D; a++) dconst += T(2) * ih2[a];
+    const T inv_d = T(1) / dconst;
+    const bool recip = !VAR && !(D == 2 && tb.axi);
     T nvs[IT];
 #pragma unroll
     for (int m = 0; m < IT; m++) {
@@ -467,7 +474,7 @@ __global__ void __launch_bounds__(256 * WIDE) k_gsrb(Plane<T> P, DevTables tb, i
                 den += w;
             }
         }
-        nvs[m] = (num - fval) / den;
+        nvs[m] = recip ? (num - fval) * inv_d : (num - fval) / den;
     }
     st_run<T, IT>(P.v + b * g::NC + colour * g::NH + qt, nvs);
 #pragma unroll
