@@ -337,6 +337,49 @@ __device__ __forceinline__ void push_ghosts(T *__restrict__ vg, const BlockCtx<D
     }
 }
 
+// push_ghosts for a run of IT cells of one colour in one row (cells i0, i0 + 2, ...):
+// on a y or z face the run's mirroring ghosts are consecutive slots of the face, written
+// as one vector; only the run's first or last cell can lie on an x face.
+template <typename T, int D, int BS, int IT>
+__device__ __forceinline__ void push_run(T *__restrict__ vg, const BlockCtx<D> &c, int64_t b, int i0, int j, int k,
+                                         const T (&nv)[IT]) {
+    using g = G<D, BS>;
+    // x faces
+    if (i0 == 0 || i0 + 2 * (IT - 1) == BS - 1) {
+        const int side = i0 == 0 ? 0 : 1;
+        const T x = side ? nv[IT - 1] : nv[0];   // selects, not a run-time index (scratch)
+        const int n = side ? c.nbr[1] : c.nbr[0];
+        if (n >= 0) {
+            vg[(int64_t)n * g::NG + g::gh(side ^ 1, j, k)] = x;
+        } else if (n == -1) {
+            const int kind = side ? c.bck[1] : c.bck[0];
+            const double val = side ? c.bcv[1] : c.bcv[0];
+            vg[b * g::NG + g::gh(side, j, k)] = bc_ghost<T>(kind, val, c.h[0], side, x);
+        }
+    }
+    // y and z faces: the tangential coordinates are (i, k) and (i, j)
+#pragma unroll
+    for (int a = 1; a < D; a++) {
+        const int coord = a == 1 ? j : k;
+        int side;
+        if (coord == 0) side = 0;
+        else if (coord == BS - 1) side = 1;
+        else continue;
+        const int f = 2 * a + side, a2 = a == 2 ? j : k;
+        const int n = side ? c.nbr[2 * a + 1] : c.nbr[2 * a];
+        if (n >= 0) {
+            st_run<T, IT>(vg + (int64_t)n * g::NG + g::gh(f ^ 1, i0, a2), nv);
+        } else if (n == -1) {
+            const int kind = side ? c.bck[2 * a + 1] : c.bck[2 * a];
+            const double val = side ? c.bcv[2 * a + 1] : c.bcv[2 * a];
+            T gv[IT];
+#pragma unroll
+            for (int m = 0; m < IT; m++) gv[m] = bc_ghost<T>(kind, val, c.h[a], side, nv[m]);
+            st_run<T, IT>(vg + b * g::NG + g::gh(f, i0, a2), gv);
+        }
+    }
+}
+
 // ------------------------------------------------------------ GS-RB sweep
 // One colour of red-black Gauss-Seidel (Sec. 2.2) for the blocks of one level, one
 // workgroup per block.  The other colour of the block and the other-colour halves of
@@ -477,13 +520,11 @@ __global__ void __launch_bounds__(256 * WIDE) k_gsrb(Plane<T> P, DevTables tb, i
         nvs[m] = recip ? (num - fval) * inv_d : (num - fval) / den;
     }
     st_run<T, IT>(P.v + b * g::NC + colour * g::NH + qt, nvs);
-#pragma unroll
-    for (int m = 0; m < IT; m++) {
-        const int q = qt + m;
-        const int row = q / g::RH, pos = q % g::RH;
+    static_assert(g::RH % IT == 0, "a run lies in one row");
+    {
+        const int row = qt / g::RH, pos = qt % g::RH;
         const int j = row % BS, k = D == 3 ? row / BS : 0;
-        const int i = 2 * pos + ((j + k + colour) & 1);
-        push_ghosts<T, D, BS>(P.vg, cx, b, i, j, k, nvs[m]);
+        push_run<T, D, BS, IT>(P.vg, cx, b, 2 * pos + ((j + k + colour) & 1), j, k, nvs);
     }
 }
 
