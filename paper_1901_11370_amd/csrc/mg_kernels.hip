@@ -1047,8 +1047,22 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
 #pragma unroll
         for (int m = 0; m < IT; m++) nvs[m] = corrected(t0 + tid * IT + m, vr[m]);
         st_run<T, IT>(P.v + b * g::NC + t0 + tid * IT, nvs);
+        if constexpr (IT % g::RH == 0) {
+            // the run is whole rows of one colour: each row's pushes as vector stores
 #pragma unroll
-        for (int m = 0; m < IT; m++) push(t0 + tid * IT + m, nvs[m]);
+            for (int r = 0; r < IT / g::RH; r++) {
+                const int tq = t0 + tid * IT + r * g::RH;
+                const int col = tq >= g::NH, row = (tq - col * g::NH) / g::RH;
+                const int j = row % BS, k = D == 3 ? row / BS : 0;
+                T seg[g::RH];
+#pragma unroll
+                for (int m = 0; m < g::RH; m++) seg[m] = nvs[r * g::RH + m];
+                push_run<T, D, BS, g::RH>(P.vg, cx, b, (j + k + col) & 1, j, k, seg);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < IT; m++) push(t0 + tid * IT + m, nvs[m]);
+        }
     } else {
 #pragma unroll
         for (int m = 0; m < IT; m++) {
