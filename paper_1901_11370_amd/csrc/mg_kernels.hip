@@ -2272,22 +2272,32 @@ __global__ void __launch_bounds__(256) k_reduce_norms(DevTables tb, const double
 
 // v64 += v32 on every leaf block (the FP64 update of iterative refinement), with the
 // same-level and boundary ghosts of the FP64 field pushed.
-// (The source is FP32 block storage, or an FP64 leaf vector when VEC.)
+// (The source is FP32 block storage, or an FP64 leaf vector when VEC.)  Each thread
+// takes one row of one colour (RH consecutive storage cells), read and written as
+// vectors, and pushes the row's ghosts with push_run.
+template <int D, int BS>
+constexpr int add_leaf_threads() { return G<D, BS>::NC / G<D, BS>::RH < 256 ? G<D, BS>::NC / G<D, BS>::RH : 256; }
 template <int D, int BS, typename S, bool VEC>
 __global__ void __launch_bounds__(256) k_add_leaf(double *v64, double *vg64, const S *src, DevTables tb,
                                                   int wg_per_block) {
     using g = G<D, BS>;
+    constexpr int R = g::RH;
     const int64_t rank = blockIdx.x / wg_per_block;
     const int64_t b = tb.leaf_blk[rank];
-    const int t = (blockIdx.x % wg_per_block) * (g::NC < 256 ? g::NC : 256) + threadIdx.x;
-    if (t >= g::NC) return;
+    const int t0 = ((blockIdx.x % wg_per_block) * add_leaf_threads<D, BS>() + threadIdx.x) * R;
+    if (t0 >= g::NC) return;
     BlockCtx<D> cx;
     cx.load(tb, b, tb.lev[b]);
-    const double nv = v64[b * g::NC + t] + (double)src[(VEC ? rank : b) * g::NC + t];
-    v64[b * g::NC + t] = nv;
-    int i, j, k;
-    g::decode(t, i, j, k);
-    push_ghosts<double, D, BS>(vg64, cx, b, i, j, k, nv);
+    double v[R];
+    S e[R];
+    ld_run<double, R>(v64 + b * g::NC + t0, v);
+    ld_run<S, R>(src + (VEC ? rank : b) * g::NC + t0, e);
+#pragma unroll
+    for (int m = 0; m < R; m++) v[m] += (double)e[m];
+    st_run<double, R>(v64 + b * g::NC + t0, v);
+    const int col = t0 >= g::NH, row = (t0 - col * g::NH) / R;
+    const int j = row % BS, k = D == 3 ? row / BS : 0;
+    push_run<double, D, BS, R>(vg64, cx, b, (j + k + col) & 1, j, k, v);
 }
 
 // dJ/deps per leaf cell from phi (v plane, ghosts filled) and lambda (blocks + ghosts).
@@ -3097,20 +3107,20 @@ void launch_reduce_norms(const Launch &L) {
 void launch_add_leaf(const Launch &L, double *v64, double *vg64, const float *v32, int nleafblk) {
     if (nleafblk <= 0) return;
     DISPATCH_DB(L, {
-        constexpr int NC = G<D, BS>::NC;
-        constexpr int TPB = NC < 256 ? NC : 256;
-        k_add_leaf<D, BS, float, false><<<(unsigned)(nleafblk * (NC / TPB)), TPB, 0, L.stream>>>(v64, vg64, v32,
-                                                                                               L.tb, NC / TPB);
+        constexpr int NT = G<D, BS>::NC / G<D, BS>::RH;   // one thread per row of one colour
+        constexpr int TPB = add_leaf_threads<D, BS>();
+        k_add_leaf<D, BS, float, false><<<(unsigned)(nleafblk * (NT / TPB)), TPB, 0, L.stream>>>(v64, vg64, v32,
+                                                                                               L.tb, NT / TPB);
     });
 }
 
 void launch_add_vec(const Launch &L, double *v64, double *vg64, const double *vec, int nleafblk) {
     if (nleafblk <= 0) return;
     DISPATCH_DB(L, {
-        constexpr int NC = G<D, BS>::NC;
-        constexpr int TPB = NC < 256 ? NC : 256;
-        k_add_leaf<D, BS, double, true><<<(unsigned)(nleafblk * (NC / TPB)), TPB, 0, L.stream>>>(v64, vg64, vec,
-                                                                                               L.tb, NC / TPB);
+        constexpr int NT = G<D, BS>::NC / G<D, BS>::RH;
+        constexpr int TPB = add_leaf_threads<D, BS>();
+        k_add_leaf<D, BS, double, true><<<(unsigned)(nleafblk * (NT / TPB)), TPB, 0, L.stream>>>(v64, vg64, vec,
+                                                                                               L.tb, NT / TPB);
     });
 }
 
