@@ -1319,12 +1319,32 @@ int mg_solve(mg_tree *t, double rel_tol, int max_cycles, int use_fmg_first, int 
             rc = run_seq(t, G_NORM, [&] { enq_residual(t, false, true); });
         }
         if (rc) return rc;
+        // Cycles whose residual cannot reach rel_tol run without the norm: before each
+        // check, the cycles that could not reach it even at twice the fastest reduction
+        // per cycle seen so far (in log terms) run unchecked.  The cycles run and the
+        // iterate are those of a check after every cycle.  On refined trees the norm
+        // also sets the parents (composite residual), so every cycle is checked there.
+        double prev_rel = 0.0, rho = 1.0;
+        int prev_cycles = 0;
         for (;;) {
             if ((rc = read_norms(t, &n))) return rc;
             rc = worst(t, n, &rel, nullptr);
             record(rel);
             if (rc) break;
+            if (cycles > prev_cycles && prev_rel > 0.0 && rel > 0.0)
+                rho = std::min(rho, std::pow(rel / prev_rel, 1.0 / (cycles - prev_cycles)));
             if (rel <= rel_tol || cycles >= max_cycles) break;
+            int skip = 0;
+            if (!t->T.refined && rho > 0.0 && rho < 1.0 && rel_tol > 0.0) {
+                const double need = std::log(rel_tol / rel) / std::log(rho * rho);
+                if (need > 1.0 && need < 1e6) skip = std::min((int)std::ceil(need) - 1, max_cycles - cycles - 1);
+            }
+            prev_rel = rel;
+            prev_cycles = cycles;
+            for (int c = 0; c < skip; c++) {
+                if ((rc = run_seq(t, G_V, [&] { d64(t).vcycle(top, all); }))) return rc;
+                cycles++;
+            }
             if ((rc = run_seq(t, G_V_NORM, [&] {
                      d64(t).vcycle(top, all);
                      enq_residual(t, false, true, true);
