@@ -242,10 +242,10 @@ int mg_residual_norms_static(mg_tree *t, double *d_norms);
 
 /* Solve to max-norm relative residual <= rel_tol: optional FMG first, then V-cycles
  * (FP64), or FP64 iterative refinement around FP32 cycles (MG_MIXED), checking the
- * norm after every cycle / refinement step.  (FP64 on trees without refinement: cycles
- * that could not reach rel_tol even at twice the fastest reduction per cycle seen so
- * far, in log terms, run without a check; the cycles run and the result are the same,
- * and mg_solve_stats lists the checked cycles only.)  With MG_MIXED and params.krylov = m > 0
+ * norm after every cycle / refinement step.  (FP64: cycles that could not reach rel_tol
+ * even at twice the fastest reduction per cycle seen so far, in log terms, run without
+ * a check; the cycles run and the result are the same, and mg_solve_stats lists the
+ * checked cycles only.)  With MG_MIXED and params.krylov = m > 0
  * the refinement is FGMRES(m) (flexible GMRES, restarted every m steps or when its
  * residual estimate falls by 1e-6; the true FP64 residual is checked at each restart);
  * one FP32 preconditioning solve counts as a cycle.  cycles_done may be NULL.

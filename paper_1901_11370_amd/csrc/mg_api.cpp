@@ -556,6 +556,7 @@ int read_norms(mg_tree *t, std::vector<double> *norms) {
 // Kinds of captured sequences.
 enum {
     G_V = 0, G_FMG, G_V_NORM, G_FMG_NORM, G_NORM, G_NORM_R32, G_IRV_NORM, G_IRFMG_NORM, G_IRV_FULL, G_IRFMG_FULL,
+    G_V_SYNC,                          // a V-cycle and the state updates of the norm (refined trees)
     G_IRV_FEWER,                       // G_IRV_NORM with 1 ... kIrFewer V-cycles (kinds G_IRV_FEWER + n - 1)
     G_KINDS = G_IRV_FEWER + 8
 };
@@ -1322,8 +1323,9 @@ int mg_solve(mg_tree *t, double rel_tol, int max_cycles, int use_fmg_first, int 
         // Cycles whose residual cannot reach rel_tol run without the norm: before each
         // check, the cycles that could not reach it even at twice the fastest reduction
         // per cycle seen so far (in log terms) run unchecked.  The cycles run and the
-        // iterate are those of a check after every cycle.  On refined trees the norm
-        // also sets the parents (composite residual), so every cycle is checked there.
+        // iterate are those of a check after every cycle: on refined trees an unchecked
+        // cycle still makes the norm's state updates (parents = mean of the children,
+        // coarse-fine ghosts), only the residual and its reduction are left out.
         double prev_rel = 0.0, rho = 1.0;
         int prev_cycles = 0;
         for (;;) {
@@ -1335,14 +1337,23 @@ int mg_solve(mg_tree *t, double rel_tol, int max_cycles, int use_fmg_first, int 
                 rho = std::min(rho, std::pow(rel / prev_rel, 1.0 / (cycles - prev_cycles)));
             if (rel <= rel_tol || cycles >= max_cycles) break;
             int skip = 0;
-            if (!t->T.refined && rho > 0.0 && rho < 1.0 && rel_tol > 0.0) {
+            if (rho > 0.0 && rho < 1.0 && rel_tol > 0.0) {
                 const double need = std::log(rel_tol / rel) / std::log(rho * rho);
                 if (need > 1.0 && need < 1e6) skip = std::min((int)std::ceil(need) - 1, max_cycles - cycles - 1);
             }
             prev_rel = rel;
             prev_cycles = cycles;
             for (int c = 0; c < skip; c++) {
-                if ((rc = run_seq(t, G_V, [&] { d64(t).vcycle(top, all); }))) return rc;
+                if (t->T.refined) {
+                    rc = run_seq(t, G_V_SYNC, [&] {
+                        Driver<double> D = d64(t);
+                        D.vcycle(top, all);
+                        D.sync(true);
+                    });
+                } else {
+                    rc = run_seq(t, G_V, [&] { d64(t).vcycle(top, all); });
+                }
+                if (rc) return rc;
                 cycles++;
             }
             if ((rc = run_seq(t, G_V_NORM, [&] {
