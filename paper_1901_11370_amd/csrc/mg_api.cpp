@@ -125,6 +125,7 @@ size_t plan(mg_tree *t, char *base) {
     size_t o_leaf = L.take<int32_t>(t->nleafblk), o_lf = L.take<int32_t>(T.ndom + 1);
     size_t o_lrank = L.take<int32_t>(nb);
     size_t o_h = L.take<double>((size_t)T.ndom * MAXLEV * 3), o_nc = L.take<int32_t>((size_t)T.ndom * MAXLEV * 3);
+    size_t o_ih2 = L.take<double>((size_t)T.ndom * MAXLEV * 3);
     size_t o_bck = L.take<int32_t>(6 * T.ndom), o_bcv = L.take<double>(6 * T.ndom), o_bc0 = L.take<double>(6 * T.ndom);
     size_t o_toff = L.take<int64_t>((size_t)T.ndom * MAXLEV);
     size_t o_ttop = L.take<int32_t>(T.ndom);
@@ -159,6 +160,9 @@ size_t plan(mg_tree *t, char *base) {
         for (size_t r = 0; r < T.leaf_blk.size(); r++) lrank[T.leaf_blk[r]] = (int32_t)r;
         put(o_lrank, lrank.data(), lrank.size() * 4);
         put(o_h, T.h.data(), T.h.size() * 8);
+        std::vector<double> ih2(T.h.size());
+        for (size_t q = 0; q < T.h.size(); q++) ih2[q] = T.h[q] > 0.0 ? 1.0 / (T.h[q] * T.h[q]) : 0.0;
+        put(o_ih2, ih2.data(), ih2.size() * 8);
         put(o_nc, T.ncell.data(), T.ncell.size() * 4);
         std::vector<int32_t> bck(6 * T.ndom);
         std::vector<double> bcv(6 * T.ndom), bc0(6 * T.ndom, 0.0);
@@ -190,6 +194,7 @@ size_t plan(mg_tree *t, char *base) {
         tb.leaf_first = (const int32_t *)P(o_lf);
         tb.leaf_rank = (const int32_t *)P(o_lrank);
         tb.h = (const double *)P(o_h);
+        tb.ih2 = (const double *)P(o_ih2);
         tb.ncell = (const int32_t *)P(o_nc);
         tb.bck = (const int32_t *)P(o_bck);
         tb.bcv = (const double *)P(o_bcv);

@@ -30,6 +30,7 @@ struct DevTables {
     const int32_t *leaf_first;// [ndom+1] first leaf rank of every domain
     const int32_t *leaf_rank; // [nb] position of a leaf block in leaf order, -1 for parents
     const double *h;          // [ndom][MAXLEV][3] grid spacing
+    const double *ih2;        // [ndom][MAXLEV][3] 1 / h^2 (computed on the host, correctly rounded)
     const int32_t *ncell;     // [ndom][MAXLEV][3] cells per dimension of the full level grid
     const int32_t *bck;       // [ndom][6] boundary kinds
     const double *bcv;        // [ndom][6] boundary values (or zeros: homogeneous)

@@ -194,12 +194,12 @@ struct Spacing {
 };
 
 __device__ __forceinline__ Spacing spacing(const DevTables &tb, int dm, int lev) {
-    const double *h = tb.h + ((size_t)dm * MAXLEV + lev) * 3;
+    const size_t o = ((size_t)dm * MAXLEV + lev) * 3;
     Spacing s;
-    for (int a = 0; a < 3; a++) s.ih2[a] = 1.0 / (h[a] * h[a]);
+    for (int a = 0; a < 3; a++) s.ih2[a] = tb.ih2[o + a];   // 1 / h^2, from the host
     s.lam = tb.lambda;
     s.axi = tb.axi;
-    s.hx = h[0];
+    s.hx = tb.h[o];
     return s;
 }
 
