@@ -26,6 +26,11 @@ constexpr double kStall = 0.999;
 constexpr int kStallSteps = 8;
 // Coarsest grids of at most this many cells (one per lane) are iterated by one wave.
 constexpr int kWaveCoarse = 64;
+// FP32 levels with at least this many parent blocks take the LDS-staged FAS kernel
+// (13.4 us against 17.5 at 512 blocks of 16^3; slower with 64: one workgroup per block
+// leaves too few to hide the memory latency, and for FP64 its 45 KB per workgroup
+// allow too few at once).
+constexpr int kFasLdsMin = 256;
 
 // Workgroups are dealt round-robin over the chip's 8 XCDs, each with its own L2.
 // Workgroup w of a launch over n blocks takes block xcd_block(w, n): XCD x gets a
@@ -925,6 +930,75 @@ __global__ void __launch_bounds__(256) k_fas(Plane<T> P, DevTables tb, int lev, 
         const T gv = P.vg[b * g::NG + t - g::NC];
         if (!((mask >> dm) & 1)) return;
         P.voldg[b * g::NG + t - g::NC] = gv;
+    }
+}
+
+// The same for 3D constant coefficients in FP32 on levels with many parent blocks
+// (kFasLdsMin or more): one workgroup per block stages v and its ghosts in LDS with 16-byte loads, writes v_old
+// from there and takes every neighbour of L v from LDS.  The
+// arithmetic is that of k_fas (Stencil::Lv with constant weights).
+template <typename T, int D, int BS>
+__global__ void __launch_bounds__(256) k_fas_lds(Plane<T> P, DevTables tb, int lev, const int32_t *list,
+                                                 uint64_t mask) {
+    using g = G<D, BS>;
+    static_assert(D == 3 && g::NC % 256 == 0 && (g::NC * sizeof(T)) % 16 == 0 && (g::NG * sizeof(T)) % 16 == 0,
+                  "block shape");
+    constexpr int NF = g::NC / 256;                 // cells per thread
+    __shared__ uint4 s_raw[(g::NC + g::NG) * sizeof(T) / 16];
+    T *s_v = reinterpret_cast<T *>(s_raw);
+    T *s_g = s_v + g::NC;
+    const int64_t b = list[blockIdx.x];
+    const int tid = threadIdx.x;
+    // every load first: v and its ghosts as vectors, then this thread's f values
+    Stager<T, 1, g::NC, g::NC, 256> cv;
+    Stager<T, 1, g::NG, g::NG, 256> cg;
+    cv.load(P.v + b * g::NC);
+    cg.load(P.vg + b * g::NG);
+    T fv[NF];
+#pragma unroll
+    for (int m = 0; m < NF; m++) fv[m] = P.f[b * g::NC + tid + m * 256];
+    // the domain test comes last so that the data loads need not wait for it (the
+    // whole workgroup leaves together, before its barrier)
+    const int dm = tb.dom[b];
+    if (!((mask >> dm) & 1)) return;
+    cv.store(s_v);
+    cg.store(s_g);
+    __syncthreads();
+    // v_old = v, ghosts included, as vectors from LDS (stored straight from the
+    // loaded registers, those would be kept in scratch memory)
+    {
+        constexpr int NVC = g::NC * sizeof(T) / 16, NVT = (g::NC + g::NG) * sizeof(T) / 16;
+        uint4 *ov = reinterpret_cast<uint4 *>(P.vold + b * g::NC);
+        uint4 *og = reinterpret_cast<uint4 *>(P.voldg + b * g::NG);
+#pragma unroll
+        for (int m = 0; m < (NVT + 255) / 256; m++) {
+            const int q = tid + m * 256;
+            if (q >= NVT) break;
+            const uint4 x = s_raw[q];
+            if (q < NVC) ov[q] = x;
+            else og[q - NVC] = x;
+        }
+    }
+    const Spacing sp = spacing(tb, dm, lev);
+#pragma unroll
+    for (int m = 0; m < NF; m++) {
+        const int t = tid + m * 256;
+        int i, j, k;
+        g::decode(t, i, j, k);
+        T nb[6];
+        nb[0] = ld<D, BS>(s_v, s_g, 0, i - 1, j, k);
+        nb[1] = ld<D, BS>(s_v, s_g, 0, i + 1, j, k);
+        nb[2] = ld<D, BS>(s_v, s_g, 0, i, j - 1, k);
+        nb[3] = ld<D, BS>(s_v, s_g, 0, i, j + 1, k);
+        nb[4] = ld<D, BS>(s_v, s_g, 0, i, j, k - 1);
+        nb[5] = ld<D, BS>(s_v, s_g, 0, i, j, k + 1);
+        const T vc = s_v[t];
+        // Stencil::Lv's operations in its order (written out: its loops would not
+        // unroll inside this one)
+        T acc = T(0);
+#pragma unroll
+        for (int f = 0; f < 2 * D; f++) acc += T(sp.ih2[f / 2]) * (nb[f] - vc);
+        P.f[b * g::NC + t] = fv[m] + (acc - T(sp.lam) * vc);
     }
 }
 
@@ -2786,6 +2860,19 @@ void K<T>::restrict_down(const Launch &L, const Plane<T> &P, int lev, int b0, in
     });
 }
 
+// The LDS-staged FAS kernel where it is the faster one (FP32, 16^3 blocks in 3D, many
+// parents); false where the per-cell kernel is to run.
+template <typename T, int D, int BS>
+static bool launch_fas_lds(const Launch &L, const Plane<T> &P, int lev, const int32_t *list, int nlist,
+                           uint64_t mask) {
+    if constexpr (sizeof(T) == 4 && D == 3 && BS == 16) {
+        if (nlist < kFasLdsMin) return false;
+        k_fas_lds<T, 3, 16><<<nlist, 256, 0, L.stream>>>(P, L.tb, lev, list, mask);
+        return true;
+    }
+    return false;
+}
+
 template <typename T>
 void K<T>::fas(const Launch &L, const Plane<T> &P, int lev, const int32_t *list, int nlist, uint64_t mask,
                bool var) {
@@ -2794,7 +2881,8 @@ void K<T>::fas(const Launch &L, const Plane<T> &P, int lev, const int32_t *list,
         constexpr int N = G<D, BS>::NC + G<D, BS>::NG;
         constexpr int WPB = (N + 255) / 256;
         if (var) k_fas<T, D, BS, true><<<nlist * WPB, 256, 0, L.stream>>>(P, L.tb, lev, list, mask, WPB);
-        else k_fas<T, D, BS, false><<<nlist * WPB, 256, 0, L.stream>>>(P, L.tb, lev, list, mask, WPB);
+        else if (!launch_fas_lds<T, D, BS>(L, P, lev, list, nlist, mask))
+            k_fas<T, D, BS, false><<<nlist * WPB, 256, 0, L.stream>>>(P, L.tb, lev, list, mask, WPB);
     });
 }
 
