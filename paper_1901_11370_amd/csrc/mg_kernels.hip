@@ -1028,7 +1028,9 @@ __global__ void __launch_bounds__(256) k_correct(Plane<T> P, DevTables tb, int l
     constexpr int NPASS = (HALF ? g::NH : g::NC) / SPLIT;
     __shared__ T s_d[NBOX];
     const int nbl = gridDim.x / SPLIT;   // parts of a block nb workgroups apart (same XCD)
-    const int64_t b = b0 + (SPLIT == 1 ? (int)blockIdx.x : (int)blockIdx.x % nbl);
+    // (one workgroup per block: the Morton-ordered blocks in one contiguous run per XCD,
+    // so siblings, whose octants and halos share cache lines of the parent, share an L2)
+    const int64_t b = b0 + (SPLIT == 1 ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x % nbl);
     const int part = SPLIT == 1 ? 0 : (int)blockIdx.x / nbl;
     const int t0 = (HALF ? g::NH : 0) + part * NPASS;   // first storage index of this part
     const int tid = threadIdx.x;
