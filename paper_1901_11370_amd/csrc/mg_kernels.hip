@@ -35,8 +35,8 @@ constexpr int kFasLdsMin = 256;
 // Workgroups are dealt round-robin over the chip's 8 XCDs, each with its own L2.
 // Workgroup w of a launch over n blocks takes block xcd_block(w, n): XCD x gets a
 // contiguous run of the (Morton-ordered) blocks, so siblings that write halves of the
-// same cache lines of their parent block run under one L2 (the restriction).  A
-// bijection on [0, n).
+// same cache lines of their parent block (the restriction), or read them (the
+// correction), run under one L2.  A bijection on [0, n).
 __device__ __forceinline__ int xcd_block(int w, int n) {
     const int q = n >> 3, r = n & 7, x = w & 7;
     return x * q + (x < r ? x : r) + (w >> 3);
@@ -934,9 +934,9 @@ __global__ void __launch_bounds__(256) k_fas(Plane<T> P, DevTables tb, int lev, 
 }
 
 // The same for 3D constant coefficients in FP32 on levels with many parent blocks
-// (kFasLdsMin or more): one workgroup per block stages v and its ghosts in LDS with 16-byte loads, writes v_old
-// from there and takes every neighbour of L v from LDS.  The
-// arithmetic is that of k_fas (Stencil::Lv with constant weights).
+// (kFasLdsMin or more): one workgroup per block stages v and its ghosts in LDS with
+// 16-byte loads, writes v_old from there and takes every neighbour of L v from LDS.
+// The arithmetic is that of k_fas (Stencil::Lv with constant weights).
 template <typename T, int D, int BS>
 __global__ void __launch_bounds__(256) k_fas_lds(Plane<T> P, DevTables tb, int lev, const int32_t *list,
                                                  uint64_t mask) {
