@@ -45,6 +45,20 @@ def test_periodic_256_full_size_mixed_against_fp64_reference():
     assert err <= 1e-7
 
 
+def test_dirichlet_box_mixed_against_fp64_reference():
+    # a 256 x 256 x 128 box (cubic cells) with phi = 0 on every face: its 128 x 128 x 64
+    # level holds 256 parent blocks, so the FP32 cycles compute the FAS right-hand side
+    # there with the LDS-staged kernel, next to physical-boundary ghosts; the mixed form's
+    # FMG step and two one-V-cycle steps against the FP64 reference's FMG + 2 V-cycles
+    rng = np.random.default_rng(21)
+    g = W.Gaussians(rng.uniform(0.1, 0.9, (8, 3)) * np.array([1.0, 1.0, 0.5]),
+                    np.where(rng.random(8) < 0.5, -1.0, 1.0), np.full(8, 0.03))
+    dom = W.Domain(3, [256, 256, 128], [0.0, 0.0, 0.0], [1.0, 1.0, 0.5], [W.DIRICHLET] * 6)
+    w = W.Workload("dirichlet_box_256x256x128", [dom], rhs=lambda i, lay: g(W.cell_centres(lay, dom)))
+    err, g_norm, o_norm = _fmg_v(w, 2, precision=1, ir_vcycles=1)
+    assert err <= 1e-7
+
+
 def test_amr_literal_full_size():
     err, g, o = _fmg_v(W.config3(nested=False), 1)
     assert err <= 1e-11 and abs(g - o) <= 1e-6 * o
