@@ -11,7 +11,9 @@ stops after the first k with |rho|^k <= 1e-8.  With rho = -1 (every face Dirichl
 the iteration only alternates; the reference's stall window ends it after 8 steps, and
 because the alternation has period two the state equals that after the paper's 1000
 steps.  On a slowly converging 8 x 1 grid the step count equals that of a brute-force
-red-black Gauss-Seidel written here with numpy, with the window on or off.
+red-black Gauss-Seidel written here with numpy, with the window on or off.  The window's
+known limit is pinned too: where the residual rises for more than 8 steps before it falls,
+the window stops the coarsest solve too early and the cycles crawl.
 
 Norms (Sec. 3.1; the L2 norm weighted by cell volume): phi = 1 in one cell of a
 refined tree, f = c everywhere, gives hand-computable residuals.
@@ -214,6 +216,32 @@ def test_window_at_the_rounding_floor():
     print(ea, eb)
     assert OracleTree.EXIT_STALL in ea and OracleTree.EXIT_NMAX in eb
     assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+
+
+def test_window_stops_early_while_the_residual_rises():
+    # the window's known limit: on this coarsest grid (Dirichlet x-, Neumann x+, periodic
+    # y, eps varying along x) the max-norm residual rises for more than 8 steps before it
+    # falls, so the window ends every coarsest solve too early and the V-cycles crawl at
+    # about 0.94 per cycle; with the paper's rule alone they contract by about 0.1 and
+    # reach 1e-10 in 9 cycles
+    from helpers import oracle_trees
+    lo, hi = [-0.3279, -0.1514], [0.4321, 0.3236]
+    dom = W.Domain(2, [32, 20], lo, hi, [D, N, P, P])
+    g = W.Gaussians(np.array([[(lo[0] + hi[0]) / 2, (lo[1] + hi[1]) / 2]]), np.array([1.0]), np.array([0.1]))
+    w = W.Workload("rising", [dom], bs=4, variable_eps=True, rhs=lambda i, lay: g(W.cell_centres(lay, dom)),
+                   eps=lambda i, lay: np.exp(np.sin(3 * W.cell_centres(lay, dom)[:, 0])))
+    out = {}
+    for stall in (8, 0):
+        o = oracle_trees(w)[0]
+        o.set_coarse_stall(stall)
+        lay = o.leaf_layout()
+        o.set_rhs(w.rhs(0, lay))
+        o.set_eps(w.eps(0, lay))
+        out[stall] = (o.solve(rel_tol=1e-10, max_cycles=20), o.last_coarse_exit)
+    (h8, exit8), (h0, _) = out[8], out[0]
+    print(len(h8), h8[-1], exit8, len(h0), h0[-1])
+    assert exit8 == OracleTree.EXIT_STALL and h8[-1] > 1e-3 and (h8[-1] / h8[1]) ** (1 / (len(h8) - 2)) > 0.9
+    assert len(h0) <= 10 and h0[-1] <= 1e-10
 
 
 def test_l2_norm_hand_worked_on_a_refined_tree():
